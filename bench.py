@@ -1,0 +1,160 @@
+"""Benchmark: spring-steps/s of the HIP mass-spring step on one MI355X, with its HBM roofline
+fraction and the FP64 oracle timed on the host as a reported CPU baseline.
+
+Workload (default): the cantilever beam of 400 x 40 x 40 nodes (640,000 masses, 8,020,476
+springs, 0.005 m spacing, per-voxel stiffness for E = 1 MPa, one end face fixed, gravity on,
+no ground, dt = 5e-5 s), synthetic and seeded.  One step = one time step of the whole body.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints ONE JSON line.  Timing: W untimed steps, then exactly K steps bracketed by
+torch.cuda.synchronize() and HIP events recorded on the stream the library launches on.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spring-steps/sec + % HBM roofline; surrogate vs plain sim evals/sec"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cantilever_400x40x40.traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_09334_amd", "csrc", "kernels.hip")
+
+
+def algorithmic_bytes(n_masses: int, n_springs: int, actuated: bool = False, batched: bool = False) -> int:
+    """Compulsory HBM traffic of one step of the per-mass CSR method: per mass read x, v and
+    write x, v (48 B), 1/m (4 B), a row offset (4 B); per spring two incidences of
+    (neighbour, k, L0) = 24 B; +2 B per spring when actuated, +4 B per mass when batched."""
+    b = 56 * n_masses + 24 * n_springs
+    if actuated:
+        b += 2 * n_springs
+    if batched:
+        b += 4 * n_masses
+    return b
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def measured_traffic(steps_per_launch: int = 1):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_sha256") != kernel_source_hash():
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(workload, steps: int):
+    import numpy as np
+
+    from oracle import lattice as L
+    from oracle import physics as P
+
+    lat = L.build(workload)
+    sys_ = P.system_from(lat, workload)
+    x, v = lat.x.copy(), np.zeros_like(lat.x)
+    x, v = P.step(sys_, x, v, 0)          # untimed first step (page-in)
+    t0 = time.perf_counter()
+    x, v = P.run(sys_, x, v, 1, steps)
+    dt = time.perf_counter() - t0
+    return {"value": lat.n_springs * steps / dt, "unit": "spring-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 NumPy steps of the full {workload.name} lattice "
+                      f"({lat.n_masses} masses, {lat.n_springs} springs), single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--fast-diff", action="store_true", help="skip the exact coordinate difference")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--nx", type=int, default=400)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (read MIB, write MIB) before the "
+                         "timed steps, as the reference kernel for the HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the step of one body "
+              "would shard into Morton slabs with halo exchange, which is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import torch
+
+    import workloads as W
+    from paper_2207_09334_amd import cronos as CR
+    from paper_2207_09334_amd import problem as PR
+
+    w = W.cantilever(args.nx, 40, 40)
+    lat = PR.build_lattice(w)
+    stream = torch.cuda.Stream()
+    flags = (CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0)
+    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block)
+    info = CR.cronos_info(sim)
+    N, S = info["n_masses"], info["n_springs"]
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    torch.cuda.synchronize()
+    CR.cronos_step(sim, args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    CR.cronos_step(sim, args.steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    x, v, step = CR.cronos_read_state(sim)
+    import numpy as np
+    if not np.isfinite(x).all():
+        print("bench.py: non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    sec_per_step = ms / 1e3 / args.steps
+    value = S / sec_per_step
+    b_step = algorithmic_bytes(N, S)
+    achieved = b_step / sec_per_step / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC, "value": value, "unit": "spring-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n_masses": N, "n_springs": S, "dt": w.dt,
+                   "block_masses": info["block_masses"], "hip_graph": not args.no_graph,
+                   "exact_difference": not args.fast_diff},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": b_step},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

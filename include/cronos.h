@@ -1,0 +1,232 @@
+/*
+ * cronos.h -- C ABI of the MI355X (gfx950) mass-spring simulator.
+ *
+ * The method is the Hookean mass-spring model of Clay et al., "A Massively-Parallel 3D
+ * Simulator for Soft and Hybrid Robots": masses x_i, v_i, m_i joined by springs
+ * (i, j, k_ij, l0_ij); each step sums per mass the gravity, external and Hooke forces of
+ * eq. (2) and integrates eqs. (3)-(4).  This library adds a contact plane with Coulomb
+ * friction and fixed masses (section "Generating a Lattice": constraints and planes;
+ * Appendix A: frictional contact planes), velocity damping (Euler-Bernoulli section) and
+ * actuated rest lengths (section "Method": springs individually rigid, actuated or
+ * functionally parameterised).
+ *
+ * Conventions for every call:
+ *  - All pointers are HOST pointers unless stated otherwise.  Input arrays are owned by the
+ *    caller and only read during the call (their contents are copied); output arrays are
+ *    caller-allocated and written in full.  No pointer is retained after a call returns.
+ *  - Arrays of 3-vectors are row-major [n][3] (x, y, z interleaved).
+ *  - Every host-facing array is in INPUT order: the library's internal space-filling-curve
+ *    renumbering never leaks out, except through cronos_layout_get which reports it.
+ *  - Errors: a negative cronos_status; no exception crosses the ABI; the detail text of the
+ *    last error on the calling thread is returned by cronos_last_error().
+ *  - Threading: a handle must not be used by two threads at once.  All device work of a
+ *    simulation is enqueued on the stream bound at creation, in call order.
+ *  - Units: SI (m, kg, s, N, N/m).  z is up; the contact plane is z = ground_z.
+ */
+#ifndef CRONOS_H
+#define CRONOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRONOS_OK = 0,
+    CRONOS_EINVAL = -1,     /* an argument or input array is invalid                        */
+    CRONOS_ENOMEM = -2,     /* host or device allocation failed                              */
+    CRONOS_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed                    */
+    CRONOS_EUNSTABLE = -4,  /* dt exceeds the explicit integrator's stability limit          */
+    CRONOS_ESTATE = -5      /* the simulated state holds NaN or Inf                          */
+} cronos_status;
+
+/* flags of cronos_desc.flags */
+#define CRONOS_ALLOW_UNSTABLE 0x1u   /* skip the stability check at creation                 */
+#define CRONOS_CHECK_LAYOUT   0x2u   /* verify the device layout against the CSR at creation  */
+#define CRONOS_NO_GRAPH       0x4u   /* enqueue steps as plain launches, not HIP graphs      */
+#define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
+                                        but a nearly relaxed spring within one spring length of
+                                        a coordinate plane loses accuracy                     */
+
+/* mass_mode / k_mode of cronos_lattice_desc */
+#define CRONOS_MASS_UNIFORM  0       /* every node gets mass_value                           */
+#define CRONOS_MASS_LUMPED   1       /* every voxel adds density*a^3/8 to each of its corners */
+#define CRONOS_K_UNIFORM     0       /* every spring gets k_uniform                          */
+#define CRONOS_K_ASSEMBLY    1       /* per-voxel stiffness: k_v/4 per edge, k_v/2 per face
+                                        diagonal, k_v per long diagonal, summed over voxels   */
+
+const char* cronos_last_error(void);
+const char* cronos_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * Lattice generation (section "Generating a Lattice", voxel-grid variant and its figure):
+ * nodes are the corners of the occupied voxels; each voxel links its corners along the 12
+ * cube edges, the 12 face diagonals and the 4 long diagonals, duplicates merged; rest
+ * lengths are nominal (a, a*sqrt2, a*sqrt3); masses and spring constants follow the chosen
+ * modes.  Canonical node order is by (z, y, x) of the integer corner coordinate, per body;
+ * springs are (i, j), i < j, sorted; an actuated spring takes the group of the
+ * lowest-(z,y,x) actuated voxel containing it.  Host-only: no device is touched.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct cronos_lattice_t* cronos_lattice;
+
+typedef struct {
+    int32_t n_bodies;                 /* >= 1                                                 */
+    const int64_t* body_voxel_offset; /* [n_bodies+1]; voxels of body b are
+                                         [off[b], off[b+1]); NULL allowed when n_bodies == 1  */
+    int64_t n_voxels;
+    const int32_t* voxels;            /* [n_voxels][3] integer voxel coordinates, |c| < 2^20,
+                                         no duplicates within a body                          */
+    const int32_t* material;          /* [n_voxels] index into material_k, or NULL (all 0)    */
+    const int32_t* group;             /* [n_voxels] actuation group >= 0, or -1 passive;
+                                         NULL = all passive                                    */
+    double spacing;                   /* voxel edge a > 0                                     */
+    double origin[3];                 /* position of integer coordinate (0,0,0)               */
+    int32_t mass_mode;                /* CRONOS_MASS_*                                        */
+    double mass_value;                /* kg per node (uniform)                                */
+    double density;                   /* kg/m^3 (lumped)                                      */
+    int32_t k_mode;                   /* CRONOS_K_*                                           */
+    double k_uniform;                 /* N/m (uniform)                                        */
+    int32_t n_materials;
+    const double* material_k;         /* [n_materials] voxel stiffness k_v (assembly)         */
+    int32_t pin_axis;                 /* -1 none; else nodes whose integer coordinate on this
+                                         axis minus the body minimum equals pin_index are fixed */
+    int32_t pin_index;
+} cronos_lattice_desc;
+
+/* Build the lattice.  Errors: EINVAL (bad sizes, duplicate voxels, bad material/axis),
+ * ENOMEM.  On success *out owns the result until cronos_lattice_destroy. */
+cronos_status cronos_lattice_build(const cronos_lattice_desc* desc, cronos_lattice* out);
+cronos_status cronos_lattice_sizes(cronos_lattice lat, int64_t* n_masses, int64_t* n_springs);
+/* Copy the lattice out; any output pointer may be NULL to skip it.
+ *   coords [N][3] int32 integer node coordinates     x [N][3] positions
+ *   mass [N], pinned [N] (0/1), body_offset [n_bodies+1] node offsets
+ *   ends [S][2] (i < j, canonical node indices), k [S], rest [S], group [S] (-1 passive)  */
+cronos_status cronos_lattice_export(cronos_lattice lat, int32_t* coords, double* x, double* mass,
+                                    uint8_t* pinned, int64_t* body_offset, int32_t* ends,
+                                    double* k, double* rest, int16_t* group);
+void cronos_lattice_destroy(cronos_lattice lat);
+
+/* ------------------------------------------------------------------------------------------
+ * Layout (section "GPU Implementation": springs and masses stored contiguously, and the
+ * mass->spring connectivity duplicated so a per-mass pass can visit its springs).  Masses
+ * are renumbered along a Morton curve per body (key bits: x at 3b, y at 3b+1, z at 3b+2 of
+ * integer coordinates relative to the body minimum; from positions quantised to 2^20 cells
+ * of the largest bbox extent when no integer coordinates are given), stable by (body, key,
+ * input index).  Springs are renumbered by (min, max) of their new endpoints; the CSR row
+ * of mass i lists (neighbour, spring) by increasing neighbour.  Host-only.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct cronos_layout_t* cronos_layout;
+
+/* x: [N][3] positions (used when grid is NULL); grid: [N][3] integer coordinates or NULL;
+ * ends: [S][2] input-order endpoints.  block_masses: masses per GPU workgroup (multiple of 64
+ * in [64, 1024]; 0 = default).  Errors: EINVAL (index out of range, i == j, spring across
+ * bodies, duplicate spring), ENOMEM. */
+cronos_status cronos_layout_build(int64_t n_masses, int32_t n_bodies, const int64_t* body_offset,
+                                  const double* x, const int32_t* grid, int64_t n_springs,
+                                  const int32_t* ends, int32_t block_masses, cronos_layout* out);
+/* perm [N] new->input mass index; row_ptr [N+1]; col [2S] neighbour (new index);
+ * sid [2S] new spring index; spring_perm [S] new->input spring index.  NULL skips. */
+cronos_status cronos_layout_get(cronos_layout lay, int32_t* perm, int64_t* row_ptr, int32_t* col,
+                                int32_t* sid, int32_t* spring_perm);
+/* Decode the sliced device layout (64-mass slices, per-workgroup halo lists, 16-bit local
+ * neighbour indices) back to the CSR and compare.  CRONOS_OK if identical, else EINVAL. */
+cronos_status cronos_layout_check(cronos_layout lay);
+/* Layout statistics: padded incidence entries, total halo entries, largest halo. */
+cronos_status cronos_layout_stats(cronos_layout lay, int64_t* sell_entries, int64_t* halo_entries,
+                                  int32_t* max_halo);
+void cronos_layout_destroy(cronos_layout lay);
+
+/* ------------------------------------------------------------------------------------------
+ * Simulation.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct cronos_sim_t* cronos_sim;
+
+typedef struct {
+    int64_t n_masses, n_springs;
+    int32_t n_bodies;             /* >= 1                                                     */
+    const int64_t* body_offset;   /* [n_bodies+1] masses of body b are contiguous in input
+                                     order; NULL allowed when n_bodies == 1                    */
+    const double* x0;             /* [N][3] initial positions                                 */
+    const double* v0;             /* [N][3] initial velocities, or NULL (zero)                */
+    const double* mass;           /* [N] > 0                                                  */
+    const uint8_t* pinned;        /* [N] 1 = fixed mass (x constant, v = 0), or NULL          */
+    const int32_t* grid;          /* [N][3] integer lattice coordinates for the space-filling
+                                     order, or NULL (positions are quantised)                 */
+    const double* fext;           /* [N][3] constant external force f_ext of eq. (2), or NULL */
+    const int32_t* ends;          /* [S][2] input mass indices, i != j, same body, no dups    */
+    const double* k;              /* [S] spring constant >= 0                                 */
+    const double* rest;           /* [S] nominal rest length L0 > 0                           */
+    const int16_t* group;         /* [S] actuation group in [0, n_groups) of its body, or -1;
+                                     NULL = all passive                                        */
+    int32_t n_groups;             /* groups per body; n_bodies * n_groups < 65535             */
+    double gravity[3];            /* m/s^2                                                    */
+    double damping;               /* per-step velocity damping fraction d in [0, 1)           */
+    double dt;                    /* > 0                                                      */
+    int32_t ground;               /* 1 = contact plane on                                     */
+    double ground_z, ground_k, ground_mu;  /* plane height, penalty stiffness (N/m), Coulomb mu */
+    int32_t device;               /* HIP device ordinal                                        */
+    void* stream;                 /* hipStream_t to enqueue on; NULL = a stream of its own    */
+    uint32_t flags;               /* CRONOS_* flags                                           */
+    int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = 256 */
+} cronos_desc;
+
+/* Per-body diagnostics (section "Energy Conservation Tests": elastic, gravitational and
+ * kinetic energy; plus the contact plane's penalty energy, momentum, centre of mass and
+ * bounding box).  Reduced in FP64 from the FP32 state. */
+typedef struct {
+    double ke, pe_spring, pe_grav, pe_contact;
+    double p[3], com[3], bbox_min[3], bbox_max[3];
+    double mass;
+    int64_t step;
+    int32_t nonfinite;            /* 1 if any x or v of the body is NaN or Inf               */
+    int32_t pad_;
+} cronos_diag;
+
+/* Validate the inputs, renumber (as cronos_layout_build), copy everything to device memory
+ * of desc->device and bind desc->stream.  Unless CRONOS_ALLOW_UNSTABLE is set, estimates the
+ * largest natural frequency w of the rest-state system (plus the contact plane's stiffness)
+ * and fails with EUNSTABLE when w * dt >= 2, where symplectic Euler diverges.
+ * Errors: EINVAL, ENOMEM, EDEVICE, EUNSTABLE. */
+cronos_status cronos_create(const cronos_desc* desc, cronos_sim* out);
+void cronos_destroy(cronos_sim sim);
+
+/* Actuation (rest length of a spring of group g in body b at t_n = n dt:
+ * L0 (1 + amp[b*G+g] sin(2 pi freq_hz t_n + phase[b*G+g]))).  phase, amp: host
+ * [n_bodies*n_groups], copied.  Errors: EINVAL (sim has no groups). */
+cronos_status cronos_set_actuation(cronos_sim sim, const double* phase, const double* amp,
+                                   double freq_hz);
+
+/* Enqueue n_steps time steps on the bound stream and return without waiting.  One step:
+ * actuated rest lengths at t_n, eq. (2) forces gathered per mass in a fixed order (no float
+ * atomics), contact normal force, v* = v + dt f/m, friction clamp, damping, x' = x + dt v',
+ * fixed masses held.  Errors: EINVAL (n_steps < 0), EDEVICE. */
+cronos_status cronos_step(cronos_sim sim, int64_t n_steps);
+
+/* Wait for the stream, then copy positions and velocities out (input order, widened to
+ * double).  x, v: [N][3] or NULL.  Errors: EDEVICE. */
+cronos_status cronos_read_state(cronos_sim sim, double* x, double* v, int64_t* step);
+
+/* Overwrite the state (input order; rounded to FP32) and the step counter n. */
+cronos_status cronos_set_state(cronos_sim sim, const double* x, const double* v, int64_t step);
+
+/* Total force of eq. (2) plus the contact normal force on every mass at the current state
+ * and t_n (input order, [N][3]), evaluated by the same gather as the step.  Blocking. */
+cronos_status cronos_eval_forces(cronos_sim sim, double* f);
+
+/* Diagnostics of every body at the current state (out: [n_bodies]).  Blocking.
+ * Returns ESTATE (after filling out) when some body holds a non-finite value. */
+cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);
+
+/* Information on the simulation: masses, springs, bodies, groups, steps taken, block size. */
+cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
+                          int32_t* block_masses, int64_t* step);
+
+/* Input-order layout of a created simulation (see cronos_layout_get). */
+cronos_status cronos_get_layout(cronos_sim sim, int32_t* perm, int64_t* row_ptr, int32_t* col,
+                                int32_t* sid, int32_t* spring_perm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRONOS_H */

@@ -1,0 +1,307 @@
+"""ctypes binding of libcronos.so: the same entry points as include/cronos.h, with NumPy
+arrays marshalled to plain pointers.  Every computation happens in the native library; this
+module only converts arguments, checks status codes and raises ``CronosError``.
+
+The library is loaded from this package's directory; importing this module fails loudly if
+it has not been built (``python -m paper_2207_09334_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcronos.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF = 0x1, 0x2, 0x4, 0x8
+MASS_UNIFORM, MASS_LUMPED = 0, 1
+K_UNIFORM, K_ASSEMBLY = 0, 1
+
+_STATUS_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EUNSTABLE: "EUNSTABLE",
+                 ESTATE: "ESTATE"}
+
+
+class CronosError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2207_09334_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+_p = C.c_void_p
+_i64, _i32, _u32, _f64 = C.c_int64, C.c_int32, C.c_uint32, C.c_double
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("n_bodies", _i32), ("body_voxel_offset", _p), ("n_voxels", _i64), ("voxels", _p),
+                ("material", _p), ("group", _p), ("spacing", _f64), ("origin", _f64 * 3),
+                ("mass_mode", _i32), ("mass_value", _f64), ("density", _f64), ("k_mode", _i32),
+                ("k_uniform", _f64), ("n_materials", _i32), ("material_k", _p), ("pin_axis", _i32),
+                ("pin_index", _i32)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("n_masses", _i64), ("n_springs", _i64), ("n_bodies", _i32), ("body_offset", _p),
+                ("x0", _p), ("v0", _p), ("mass", _p), ("pinned", _p), ("grid", _p), ("fext", _p),
+                ("ends", _p), ("k", _p), ("rest", _p), ("group", _p), ("n_groups", _i32),
+                ("gravity", _f64 * 3), ("damping", _f64), ("dt", _f64), ("ground", _i32),
+                ("ground_z", _f64), ("ground_k", _f64), ("ground_mu", _f64), ("device", _i32),
+                ("stream", _p), ("flags", _u32), ("block_masses", _i32)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("ke", _f64), ("pe_spring", _f64), ("pe_grav", _f64), ("pe_contact", _f64),
+                ("p", _f64 * 3), ("com", _f64 * 3), ("bbox_min", _f64 * 3), ("bbox_max", _f64 * 3),
+                ("mass", _f64), ("step", _i64), ("nonfinite", _i32), ("pad_", _i32)]
+
+    def as_dict(self) -> dict:
+        return {"ke": self.ke, "pe_spring": self.pe_spring, "pe_grav": self.pe_grav,
+                "pe_contact": self.pe_contact, "p": np.array(self.p[:]), "com": np.array(self.com[:]),
+                "bbox_min": np.array(self.bbox_min[:]), "bbox_max": np.array(self.bbox_max[:]),
+                "mass": self.mass, "step": self.step, "nonfinite": bool(self.nonfinite)}
+
+
+_SIGS = {
+    "cronos_last_error": (C.c_char_p, []),
+    "cronos_version": (C.c_char_p, []),
+    "cronos_lattice_build": (C.c_int, [C.POINTER(LatticeDesc), C.POINTER(_p)]),
+    "cronos_lattice_sizes": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64)]),
+    "cronos_lattice_export": (C.c_int, [_p] + [_p] * 9),
+    "cronos_lattice_destroy": (None, [_p]),
+    "cronos_layout_build": (C.c_int, [_i64, _i32, _p, _p, _p, _i64, _p, _i32, C.POINTER(_p)]),
+    "cronos_layout_get": (C.c_int, [_p] * 6),
+    "cronos_layout_check": (C.c_int, [_p]),
+    "cronos_layout_stats": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32)]),
+    "cronos_layout_destroy": (None, [_p]),
+    "cronos_create": (C.c_int, [C.POINTER(Desc), C.POINTER(_p)]),
+    "cronos_destroy": (None, [_p]),
+    "cronos_set_actuation": (C.c_int, [_p, _p, _p, _f64]),
+    "cronos_step": (C.c_int, [_p, _i64]),
+    "cronos_read_state": (C.c_int, [_p, _p, _p, C.POINTER(_i64)]),
+    "cronos_set_state": (C.c_int, [_p, _p, _p, _i64]),
+    "cronos_eval_forces": (C.c_int, [_p, _p]),
+    "cronos_diagnostics": (C.c_int, [_p, C.POINTER(Diag)]),
+    "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
+                              C.POINTER(_i64)]),
+    "cronos_get_layout": (C.c_int, [_p] * 6),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)        # AttributeError = the library lacks a declared entry point
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+def _arr(a, dtype, shape=None):
+    if a is None:
+        return None
+    out = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None:
+        out = out.reshape(shape)
+    return out
+
+
+def _check(st: int, allow=()):
+    if st != OK and st not in allow:
+        raise CronosError(st, _lib.cronos_last_error().decode())
+    return st
+
+
+def cronos_last_error() -> str:
+    return _lib.cronos_last_error().decode()
+
+
+def cronos_version() -> str:
+    return _lib.cronos_version().decode()
+
+
+# ------------------------------------------------------------------------------ lattice
+
+class Lattice:
+    """Result of cronos_lattice_build, exported to NumPy (input order)."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    @property
+    def n_masses(self):
+        return len(self.mass)
+
+    @property
+    def n_springs(self):
+        return len(self.k)
+
+
+def cronos_lattice_build(voxels, spacing, origin=(0.0, 0.0, 0.0), body_voxel_offset=None, material=None,
+                         group=None, mass_mode=MASS_UNIFORM, mass_value=0.0, density=0.0, k_mode=K_UNIFORM,
+                         k_uniform=0.0, material_k=None, pin_axis=-1, pin_index=0) -> Lattice:
+    vox = _arr(voxels, np.int32, (-1, 3))
+    bvo = _arr(body_voxel_offset, np.int64)
+    mat = _arr(material, np.int32)
+    grp = _arr(group, np.int32)
+    mk = _arr(material_k, np.float64)
+    d = LatticeDesc(n_bodies=1 if bvo is None else len(bvo) - 1, body_voxel_offset=_ptr(bvo),
+                    n_voxels=len(vox), voxels=_ptr(vox), material=_ptr(mat), group=_ptr(grp),
+                    spacing=spacing, origin=(_f64 * 3)(*origin), mass_mode=mass_mode, mass_value=mass_value,
+                    density=density, k_mode=k_mode, k_uniform=k_uniform,
+                    n_materials=0 if mk is None else len(mk), material_k=_ptr(mk), pin_axis=pin_axis,
+                    pin_index=pin_index)
+    h = _p()
+    _check(_lib.cronos_lattice_build(C.byref(d), C.byref(h)))
+    try:
+        n, s = _i64(), _i64()
+        _check(_lib.cronos_lattice_sizes(h, C.byref(n), C.byref(s)))
+        n, s = n.value, s.value
+        nb = d.n_bodies
+        out = dict(coords=np.empty((n, 3), np.int32), x=np.empty((n, 3)), mass=np.empty(n),
+                   pinned=np.empty(n, np.uint8), body_offset=np.empty(nb + 1, np.int64),
+                   ends=np.empty((s, 2), np.int32), k=np.empty(s), rest=np.empty(s), group=np.empty(s, np.int16))
+        _check(_lib.cronos_lattice_export(h, *[_ptr(out[f]) for f in
+                                               ("coords", "x", "mass", "pinned", "body_offset", "ends", "k",
+                                                "rest", "group")]))
+    finally:
+        _lib.cronos_lattice_destroy(h)
+    return Lattice(**out)
+
+
+# ------------------------------------------------------------------------------ layout
+
+def cronos_layout_build(ends, n_masses, body_offset=None, x=None, grid=None, block_masses=0, check=False):
+    """Returns dict(perm, row_ptr, col, sid, spring_perm, sell_entries, halo_entries, max_halo)."""
+    e = _arr(ends, np.int32, (-1, 2))
+    bo = _arr(body_offset, np.int64)
+    xx = _arr(x, np.float64, (-1, 3))
+    gg = _arr(grid, np.int32, (-1, 3))
+    h = _p()
+    _check(_lib.cronos_layout_build(n_masses, 1 if bo is None else len(bo) - 1, _ptr(bo), _ptr(xx), _ptr(gg),
+                                    len(e), _ptr(e), block_masses, C.byref(h)))
+    try:
+        S = len(e)
+        out = dict(perm=np.empty(n_masses, np.int32), row_ptr=np.empty(n_masses + 1, np.int64),
+                   col=np.empty(2 * S, np.int32), sid=np.empty(2 * S, np.int32), spring_perm=np.empty(S, np.int32))
+        _check(_lib.cronos_layout_get(h, *[_ptr(out[f]) for f in ("perm", "row_ptr", "col", "sid", "spring_perm")]))
+        if check:
+            _check(_lib.cronos_layout_check(h))
+        a, b, c = _i64(), _i64(), _i32()
+        _check(_lib.cronos_layout_stats(h, C.byref(a), C.byref(b), C.byref(c)))
+        out.update(sell_entries=a.value, halo_entries=b.value, max_halo=c.value)
+    finally:
+        _lib.cronos_layout_destroy(h)
+    return out
+
+
+# ------------------------------------------------------------------------------ simulation
+
+class Sim:
+    """Owner of a cronos_sim handle (destroyed with the object)."""
+
+    def __init__(self, handle, n_masses, n_springs, n_bodies, n_groups):
+        self.handle = handle
+        self.n_masses, self.n_springs, self.n_bodies, self.n_groups = n_masses, n_springs, n_bodies, n_groups
+
+    def close(self):
+        if self.handle:
+            _lib.cronos_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cronos_create(x0, mass, ends, k, rest, *, v0=None, pinned=None, grid=None, fext=None, group=None,
+                  n_groups=0, body_offset=None, gravity=(0.0, 0.0, -9.81), damping=0.0, dt=1e-4, ground=False,
+                  ground_z=0.0, ground_k=0.0, ground_mu=0.0, device=0, stream=None, flags=0,
+                  block_masses=0) -> Sim:
+    x0 = _arr(x0, np.float64, (-1, 3))
+    n = len(x0)
+    ends = _arr(ends, np.int32, (-1, 2))
+    keep = dict(x0=x0, mass=_arr(mass, np.float64), ends=ends, k=_arr(k, np.float64), rest=_arr(rest, np.float64),
+                v0=_arr(v0, np.float64, (-1, 3)), pinned=_arr(pinned, np.uint8), grid=_arr(grid, np.int32, (-1, 3)),
+                fext=_arr(fext, np.float64, (-1, 3)), group=_arr(group, np.int16),
+                body_offset=_arr(body_offset, np.int64))
+    nb = 1 if keep["body_offset"] is None else len(keep["body_offset"]) - 1
+    d = Desc(n_masses=n, n_springs=len(ends), n_bodies=nb, body_offset=_ptr(keep["body_offset"]),
+             x0=_ptr(x0), v0=_ptr(keep["v0"]), mass=_ptr(keep["mass"]), pinned=_ptr(keep["pinned"]),
+             grid=_ptr(keep["grid"]), fext=_ptr(keep["fext"]), ends=_ptr(ends), k=_ptr(keep["k"]),
+             rest=_ptr(keep["rest"]), group=_ptr(keep["group"]), n_groups=n_groups,
+             gravity=(_f64 * 3)(*gravity), damping=damping, dt=dt, ground=int(bool(ground)), ground_z=ground_z,
+             ground_k=ground_k, ground_mu=ground_mu, device=device, stream=stream, flags=flags,
+             block_masses=block_masses)
+    h = _p()
+    _check(_lib.cronos_create(C.byref(d), C.byref(h)))
+    return Sim(h, n, len(ends), nb, n_groups)
+
+
+def cronos_destroy(sim: Sim):
+    sim.close()
+
+
+def cronos_set_actuation(sim: Sim, phase, amp, freq_hz: float):
+    ph, am = _arr(phase, np.float64), _arr(amp, np.float64)
+    if len(ph) != sim.n_bodies * sim.n_groups or len(am) != len(ph):
+        raise CronosError(EINVAL, "phase/amp must have n_bodies * n_groups entries")
+    _check(_lib.cronos_set_actuation(sim.handle, _ptr(ph), _ptr(am), freq_hz))
+
+
+def cronos_step(sim: Sim, n_steps: int):
+    _check(_lib.cronos_step(sim.handle, int(n_steps)))
+
+
+def cronos_read_state(sim: Sim, want_x=True, want_v=True):
+    x = np.empty((sim.n_masses, 3)) if want_x else None
+    v = np.empty((sim.n_masses, 3)) if want_v else None
+    step = _i64()
+    _check(_lib.cronos_read_state(sim.handle, _ptr(x), _ptr(v), C.byref(step)))
+    return x, v, step.value
+
+
+def cronos_set_state(sim: Sim, x=None, v=None, step: int = 0):
+    xx, vv = _arr(x, np.float64, (-1, 3)), _arr(v, np.float64, (-1, 3))
+    for a in (xx, vv):
+        if a is not None and len(a) != sim.n_masses:
+            raise CronosError(EINVAL, "state arrays must have n_masses rows")
+    _check(_lib.cronos_set_state(sim.handle, _ptr(xx), _ptr(vv), int(step)))
+
+
+def cronos_eval_forces(sim: Sim) -> np.ndarray:
+    f = np.empty((sim.n_masses, 3))
+    _check(_lib.cronos_eval_forces(sim.handle, _ptr(f)))
+    return f
+
+
+def cronos_diagnostics(sim: Sim, allow_nonfinite=False) -> list:
+    out = (Diag * sim.n_bodies)()
+    _check(_lib.cronos_diagnostics(sim.handle, out), allow=(ESTATE,) if allow_nonfinite else ())
+    return [o.as_dict() for o in out]
+
+
+def cronos_info(sim: Sim) -> dict:
+    n, s, st = _i64(), _i64(), _i64()
+    nb, blk = _i32(), _i32()
+    _check(_lib.cronos_info(sim.handle, C.byref(n), C.byref(s), C.byref(nb), C.byref(blk), C.byref(st)))
+    return dict(n_masses=n.value, n_springs=s.value, n_bodies=nb.value, block_masses=blk.value, step=st.value)
+
+
+def cronos_get_layout(sim: Sim) -> dict:
+    S = sim.n_springs
+    out = dict(perm=np.empty(sim.n_masses, np.int32), row_ptr=np.empty(sim.n_masses + 1, np.int64),
+               col=np.empty(2 * S, np.int32), sid=np.empty(2 * S, np.int32), spring_perm=np.empty(S, np.int32))
+    _check(_lib.cronos_get_layout(sim.handle, *[_ptr(out[f]) for f in ("perm", "row_ptr", "col", "sid",
+                                                                       "spring_perm")]))
+    return out

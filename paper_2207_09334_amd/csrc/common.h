@@ -1,0 +1,58 @@
+// Internal helpers shared by the host sources of the library (error reporting, sizes).
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "cronos.h"
+
+namespace cronos {
+
+// Sets the calling thread's last-error text and returns the status.
+cronos_status fail(cronos_status st, const char* fmt, ...);
+void clear_error();
+
+// Masses per 64-lane slice: one wavefront owns one slice, one lane per mass.
+constexpr int kSlice = 64;
+// Default masses per workgroup (4 wavefronts).
+constexpr int kDefaultBlock = 256;
+// Marker of a passive (not actuated) incidence in the 16-bit group array.
+constexpr uint16_t kPassive = 0xFFFF;
+
+// Host-side renumbering, CSR incidence list and the sliced device layout built from it.
+struct Layout {
+    int64_t n = 0, s = 0;
+    int32_t nb = 1;
+    std::vector<int64_t> body_off;      // [nb+1]
+    std::vector<int32_t> perm, inv;     // new->input, input->new
+    std::vector<int32_t> ends;          // [2S] new endpoints (min, max), sorted
+    std::vector<int32_t> spring_perm;   // new spring -> input spring
+    std::vector<int64_t> row_ptr;       // [N+1]
+    std::vector<int32_t> col, sid;      // [2S]
+
+    // sliced layout: slice s covers new masses [64 s, 64 s + 64); workgroup b covers
+    // [b*block, (b+1)*block) and stages its masses plus its halo in LDS.
+    int32_t block = kDefaultBlock;
+    int64_t nblk = 0, nslice = 0;
+    std::vector<int32_t> slice_ptr;     // [nslice+1] first entry of each slice
+    std::vector<uint16_t> nbr_local;    // [entries] LDS slot of the neighbour
+    std::vector<int32_t> entry_csr;     // [entries] CSR position, -1 = padding
+    std::vector<int32_t> halo_ptr;      // [nblk+1]
+    std::vector<int32_t> halo_idx;      // halo masses of each workgroup (new indices)
+    int32_t max_halo = 0;
+};
+
+// Builds everything in Layout (renumbering, CSR, slices, halos).  Validates the springs.
+cronos_status build_layout(int64_t n, int32_t nb, const int64_t* body_offset, const double* x,
+                           const int32_t* grid, int64_t s, const int32_t* ends, int32_t block,
+                           Layout& out);
+cronos_status check_layout(const Layout& lay);
+
+}  // namespace cronos
+
+struct cronos_layout_t {
+    cronos::Layout lay;
+};

@@ -1,0 +1,57 @@
+// Launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cronos {
+
+struct StepParams {
+    float dt;
+    float damp;          // 1 - d
+    float gx, gy, gz;
+    float ground_z, ground_k, ground_mu;
+    int ground;          // contact plane on
+    int exact;           // exact coordinate differences (see hooke in kernels.hip)
+};
+
+// Device-resident layout and state of one simulation (all arrays in Morton order).
+struct DeviceArrays {
+    int64_t n = 0;          // masses
+    int32_t block = 256;    // masses (= threads) per workgroup
+    int64_t nblk = 0;
+    int32_t lds_slots = 0;  // block + largest halo
+    float4* x[2] = {nullptr, nullptr};   // (x, y, z, 1/m); 1/m = 0 marks a fixed mass
+    float* v[2] = {nullptr, nullptr};    // [n][3]
+    float* mass = nullptr;               // [n]
+    float* fext = nullptr;               // [n][3] or null
+    int32_t* slice_ptr = nullptr;
+    uint16_t* nbr = nullptr;
+    float2* kl = nullptr;                // (k, L0) per entry
+    uint16_t* grp = nullptr;             // per entry index into factor[], or null
+    int32_t* halo_ptr = nullptr;
+    int32_t* halo_idx = nullptr;
+    // actuation
+    int32_t n_factor = 0;                // bodies * groups (factor[n_factor] = 1 for passive)
+    double* phase = nullptr;
+    double* amp = nullptr;
+    float* factor = nullptr;             // 1 + A sin(...) per (body, group), FP32
+    long long* step_ctr = nullptr;       // device step counter n
+    // diagnostics
+    int32_t n_chunks = 0;
+    int32_t nb = 1;
+    int4* chunks = nullptr;              // (block, first mass, end mass, body)
+    int32_t* body_chunk = nullptr;       // [nb+1] chunk offsets of each body
+    double* chunk_part = nullptr;        // [n_chunks][kDiagFields]
+    double* body_out = nullptr;          // [nb][kDiagFields]
+    float* fout = nullptr;               // [n][3] force output
+};
+
+constexpr int kDiagFields = 20;  // ke, pe_s, pe_g, pe_c, p3, mx3, mass, min3, max3, nonfinite
+
+hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
+hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st);
+hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
+hipError_t launch_diagnostics(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
+
+}  // namespace cronos

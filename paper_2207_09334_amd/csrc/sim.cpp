@@ -1,0 +1,597 @@
+// Simulation handle: validation, renumbering, device upload, step enqueueing (plain launches
+// or HIP graphs of several steps), state read-back, force evaluation and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace cronos {
+
+namespace {
+thread_local std::string g_err;
+}
+
+cronos_status fail(cronos_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+}  // namespace cronos
+
+using cronos::fail;
+
+extern "C" const char* cronos_last_error(void) { return cronos::g_err.c_str(); }
+extern "C" const char* cronos_version(void) { return "cronos-gfx950 0.1"; }
+
+namespace {
+
+constexpr int kGraphSteps = 16;  // steps per captured graph (even: ping-pong parity preserved)
+
+#define HIP_TRY(expr)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(CRONOS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct cronos_sim_t {
+    cronos::Layout lay;
+    cronos::DeviceArrays d;
+    cronos::StepParams p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cur = 0;
+    int64_t step = 0;
+    int32_t nb = 1, n_groups = 0;
+    double dt = 0.0, omega = 0.0;
+    bool actuated = false, use_graph = true;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::vector<float> inv_m;            // new order
+    float4* h_x = nullptr;               // pinned staging
+    float* h_v = nullptr;
+    float* h_f = nullptr;
+    double* h_diag = nullptr;
+};
+
+namespace {
+
+void free_device(cronos_sim_t* s) {
+    cronos::DeviceArrays& d = s->d;
+    void* ptrs[] = {d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
+                    d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
+                    d.body_out, d.fout};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& g : s->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (s->h_x) (void)hipHostFree(s->h_x);
+    if (s->h_v) (void)hipHostFree(s->h_v);
+    if (s->h_f) (void)hipHostFree(s->h_f);
+    if (s->h_diag) (void)hipHostFree(s->h_diag);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+template <typename T>
+cronos_status upload(T** dst, const T* src, size_t count) {
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)dst, count * sizeof(T)) != hipSuccess) return fail(CRONOS_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+    if (src) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return CRONOS_OK;
+}
+
+#define TRY(expr)                                \
+    do {                                         \
+        cronos_status st_ = (expr);              \
+        if (st_ != CRONOS_OK) return st_;        \
+    } while (0)
+
+// Largest natural frequency of the rest-state system (springs k n n^T plus the contact
+// plane's k_g on z) among free masses.  Gershgorin first; if that bound is not conclusive,
+// power iteration on M^-1/2 K M^-1/2.
+double omega_max(const cronos::Layout& L, const cronos_desc& d, const std::vector<double>& xn,
+                 const std::vector<double>& mn, const std::vector<uint8_t>& pin, const std::vector<double>& ks,
+                 bool& conclusive_gersh, double dt) {
+    const int64_t n = L.n, s = L.s;
+    std::vector<double> nx(3 * s);
+    std::vector<double> rowsum(n, 0.0);
+    for (int64_t q = 0; q < s; ++q) {
+        int32_t a = L.ends[2 * q], b = L.ends[2 * q + 1];
+        double dv[3], len2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            dv[c] = xn[3 * b + c] - xn[3 * a + c];
+            len2 += dv[c] * dv[c];
+        }
+        double len = std::sqrt(len2);
+        double l1 = 0.0, mx = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            nx[3 * q + c] = len > 0 ? dv[c] / len : 0.0;
+            l1 += std::fabs(nx[3 * q + c]);
+            mx = std::max(mx, std::fabs(nx[3 * q + c]));
+        }
+        double g = 2.0 * ks[q] * mx * l1;
+        rowsum[a] += g;
+        rowsum[b] += g;
+    }
+    double kg = d.ground ? d.ground_k : 0.0;
+    double gersh = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (!pin[i]) gersh = std::max(gersh, (rowsum[i] + kg) / mn[i]);
+    conclusive_gersh = std::sqrt(gersh) * dt < 2.0;
+    if (conclusive_gersh) return std::sqrt(gersh);
+    // power iteration on B = M^-1/2 K M^-1/2 over free DOFs
+    std::vector<double> u(3 * n), w(3 * n);
+    for (int64_t i = 0; i < 3 * n; ++i) u[i] = pin[i / 3] ? 0.0 : 1.0 + 0.37 * std::sin(0.91 * (double)i);
+    double lam = 0.0;
+    for (int it = 0; it < 400; ++it) {
+        double nrm = 0.0;
+        for (double v : u) nrm += v * v;
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) break;
+        for (double& v : u) v /= nrm;
+        std::fill(w.begin(), w.end(), 0.0);
+        for (int64_t q = 0; q < s; ++q) {
+            int32_t a = L.ends[2 * q], b = L.ends[2 * q + 1];
+            double sa = 1.0 / std::sqrt(mn[a]), sb = 1.0 / std::sqrt(mn[b]);
+            double proj = 0.0;
+            for (int c = 0; c < 3; ++c) proj += nx[3 * q + c] * (u[3 * b + c] * sb - u[3 * a + c] * sa);
+            for (int c = 0; c < 3; ++c) {
+                double f = ks[q] * proj * nx[3 * q + c];
+                w[3 * a + c] -= f * sa;
+                w[3 * b + c] += f * sb;
+            }
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (pin[i]) {
+                w[3 * i] = w[3 * i + 1] = w[3 * i + 2] = 0.0;
+                continue;
+            }
+            w[3 * i + 2] += kg / mn[i] * u[3 * i + 2];
+        }
+        // Rayleigh quotient of the unit vector u: w = B u
+        double lam_new = 0.0;
+        for (int64_t i = 0; i < 3 * n; ++i) lam_new += u[i] * w[i];
+        if (it > 20 && std::fabs(lam_new - lam) <= 1e-7 * std::fabs(lam_new)) {
+            lam = lam_new;
+            break;
+        }
+        lam = lam_new;
+        u.swap(w);
+    }
+    return std::sqrt(std::max(lam, 0.0));
+}
+
+cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
+    for (int64_t k = 0; k < n; ++k) {
+        if (s->actuated) HIP_TRY(cronos::launch_actuation(s->d, s->omega, s->dt, 1, s->stream));
+        HIP_TRY(cronos::launch_step(s->d, s->cur, s->p, s->stream));
+        s->cur ^= 1;
+    }
+    return CRONOS_OK;
+}
+
+cronos_status ensure_graph(cronos_sim_t* s) {
+    if (s->graph[s->cur]) return CRONOS_OK;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int cur0 = s->cur;
+    cronos_status st = enqueue_plain(s, kGraphSteps);
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    s->cur = cur0;
+    if (st != CRONOS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->graph[cur0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return CRONOS_OK;
+}
+
+}  // namespace
+
+extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
+    cronos::clear_error();
+    if (!d || !out) return fail(CRONOS_EINVAL, "create: NULL argument");
+    *out = nullptr;
+    const int64_t n = d->n_masses, s = d->n_springs;
+    if (n < 1) return fail(CRONOS_EINVAL, "create: n_masses < 1");
+    if (s < 0) return fail(CRONOS_EINVAL, "create: n_springs < 0");
+    if (!d->x0 || !d->mass) return fail(CRONOS_EINVAL, "create: x0 and mass are required");
+    if (s > 0 && (!d->ends || !d->k || !d->rest)) return fail(CRONOS_EINVAL, "create: ends, k, rest are required");
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(CRONOS_EINVAL, "create: dt must be > 0");
+    if (!(d->damping >= 0.0 && d->damping < 1.0)) return fail(CRONOS_EINVAL, "create: damping must be in [0, 1)");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(d->gravity[c])) return fail(CRONOS_EINVAL, "create: gravity not finite");
+    if (d->ground && (!std::isfinite(d->ground_z) || !(d->ground_k >= 0.0) || !(d->ground_mu >= 0.0)))
+        return fail(CRONOS_EINVAL, "create: bad contact plane parameters");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(d->mass[i] > 0.0) || !std::isfinite(d->mass[i])) return fail(CRONOS_EINVAL, "create: mass %lld not > 0", (long long)i);
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(d->x0[3 * i + c])) return fail(CRONOS_EINVAL, "create: x0 not finite");
+            if (d->v0 && !std::isfinite(d->v0[3 * i + c])) return fail(CRONOS_EINVAL, "create: v0 not finite");
+            if (d->fext && !std::isfinite(d->fext[3 * i + c])) return fail(CRONOS_EINVAL, "create: fext not finite");
+        }
+    }
+    for (int64_t q = 0; q < s; ++q) {
+        if (!(d->k[q] >= 0.0) || !std::isfinite(d->k[q])) return fail(CRONOS_EINVAL, "create: k[%lld] invalid", (long long)q);
+        if (!(d->rest[q] > 0.0) || !std::isfinite(d->rest[q])) return fail(CRONOS_EINVAL, "create: rest[%lld] invalid", (long long)q);
+        if (d->group && (d->group[q] < -1 || d->group[q] >= d->n_groups))
+            return fail(CRONOS_EINVAL, "create: group[%lld] out of range", (long long)q);
+    }
+    if (d->group && ((int64_t)std::max(d->n_bodies, 1) * d->n_groups >= 65535 || d->n_groups < 1))
+        return fail(CRONOS_EINVAL, "create: n_bodies * n_groups must be in [1, 65535)");
+
+    auto* sim = new (std::nothrow) cronos_sim_t;
+    if (!sim) return fail(CRONOS_ENOMEM, "create: out of memory");
+    cronos_status st;
+    try {
+        st = cronos::build_layout(n, std::max(d->n_bodies, 1), d->body_offset, d->x0, d->grid, s, d->ends,
+                                  d->block_masses, sim->lay);
+    } catch (const std::bad_alloc&) {
+        st = fail(CRONOS_ENOMEM, "create: out of memory");
+    }
+    if (st != CRONOS_OK) {
+        delete sim;
+        return st;
+    }
+    if ((d->flags & CRONOS_CHECK_LAYOUT) && (st = cronos::check_layout(sim->lay)) != CRONOS_OK) {
+        delete sim;
+        return st;
+    }
+    const cronos::Layout& L = sim->lay;
+    sim->nb = L.nb;
+    sim->n_groups = d->group ? d->n_groups : 0;
+    sim->actuated = d->group != nullptr;
+    sim->dt = d->dt;
+    sim->device = d->device;
+    sim->use_graph = !(d->flags & CRONOS_NO_GRAPH);
+
+    // ---- host arrays in the new order
+    std::vector<double> xn(3 * n), mn(n), ks(s);
+    std::vector<uint8_t> pin(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t o = L.perm[i];
+        for (int c = 0; c < 3; ++c) xn[3 * i + c] = d->x0[3 * o + c];
+        mn[i] = d->mass[o];
+        pin[i] = d->pinned ? (d->pinned[o] != 0) : 0;
+    }
+    for (int64_t q = 0; q < s; ++q) ks[q] = d->k[L.spring_perm[q]];
+    if (!(d->flags & CRONOS_ALLOW_UNSTABLE)) {
+        bool by_gersh = false;
+        double w = omega_max(L, *d, xn, mn, pin, ks, by_gersh, d->dt);
+        if (w * d->dt >= 2.0) {
+            delete sim;
+            return fail(CRONOS_EUNSTABLE, "create: largest natural frequency %.6g rad/s times dt = %.4g >= 2: "
+                        "symplectic Euler diverges (set CRONOS_ALLOW_UNSTABLE to override)", w, w * d->dt);
+        }
+    }
+
+    std::vector<float4> hx(n);
+    std::vector<float> hv(3 * n, 0.0f), hm(n), hf;
+    sim->inv_m.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t o = L.perm[i];
+        float im = pin[i] ? 0.0f : (float)(1.0 / mn[i]);
+        sim->inv_m[i] = im;
+        hx[i] = make_float4((float)xn[3 * i], (float)xn[3 * i + 1], (float)xn[3 * i + 2], im);
+        if (d->v0 && !pin[i])
+            for (int c = 0; c < 3; ++c) hv[3 * i + c] = (float)d->v0[3 * o + c];
+        hm[i] = (float)mn[i];
+    }
+    if (d->fext) {
+        hf.resize(3 * n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) hf[3 * i + c] = (float)d->fext[3 * L.perm[i] + c];
+    }
+    const int64_t entries = L.slice_ptr.back();
+    std::vector<float2> hkl(entries);
+    std::vector<uint16_t> hg;
+    const int32_t n_factor = sim->nb * sim->n_groups;
+    if (sim->actuated) hg.assign(entries, (uint16_t)n_factor);
+    std::vector<int32_t> spring_body;
+    if (sim->actuated) {
+        spring_body.resize(s);
+        int32_t b = 0;
+        for (int64_t q = 0; q < s; ++q) {
+            int32_t a = L.ends[2 * q];
+            while (a >= L.body_off[b + 1]) ++b;
+            while (a < L.body_off[b]) --b;
+            spring_body[q] = b;
+        }
+    }
+    for (int64_t e = 0; e < entries; ++e) {
+        int32_t pos = L.entry_csr[e];
+        if (pos < 0) {
+            hkl[e] = make_float2(0.0f, 0.0f);
+            continue;
+        }
+        int32_t sn = L.sid[pos], si = L.spring_perm[sn];
+        hkl[e] = make_float2((float)d->k[si], (float)d->rest[si]);
+        if (sim->actuated && d->group[si] >= 0) hg[e] = (uint16_t)(spring_body[sn] * sim->n_groups + d->group[si]);
+    }
+
+    // diagnostics chunks: workgroup blocks split at body boundaries
+    std::vector<int4> chunks;
+    std::vector<int32_t> body_chunk(sim->nb + 1, 0);
+    {
+        int32_t b = 0;
+        for (int64_t blk = 0; blk < L.nblk; ++blk) {
+            int64_t m0 = blk * L.block, m1 = std::min<int64_t>(n, m0 + L.block);
+            while (m0 < m1) {
+                while (m0 >= L.body_off[b + 1]) {
+                    ++b;
+                    body_chunk[b] = (int32_t)chunks.size();
+                }
+                int64_t e = std::min<int64_t>(m1, L.body_off[b + 1]);
+                chunks.push_back(make_int4((int)blk, (int)m0, (int)e, b));
+                m0 = e;
+            }
+        }
+        for (int32_t bb = b + 1; bb <= sim->nb; ++bb) body_chunk[bb] = (int32_t)chunks.size();
+    }
+
+    // ---- device
+    cronos::DeviceArrays& D = sim->d;
+    D.n = n;
+    D.block = L.block;
+    D.nblk = L.nblk;
+    D.lds_slots = L.block + L.max_halo;
+    D.nb = sim->nb;
+    D.n_factor = n_factor;
+    D.n_chunks = (int32_t)chunks.size();
+    if (hipSetDevice(d->device) != hipSuccess) {
+        delete sim;
+        return fail(CRONOS_EDEVICE, "create: hipSetDevice(%d) failed", d->device);
+    }
+    if ((size_t)D.lds_slots * sizeof(float4) > 160 * 1024) {
+        delete sim;
+        return fail(CRONOS_EINVAL, "create: workgroup halo needs %zu bytes of LDS", (size_t)D.lds_slots * sizeof(float4));
+    }
+    st = [&]() -> cronos_status {
+        if (d->stream) {
+            sim->stream = (hipStream_t)d->stream;
+        } else {
+            HIP_TRY(hipStreamCreateWithFlags(&sim->stream, hipStreamNonBlocking));
+            sim->own_stream = true;
+        }
+        TRY(upload(&D.x[0], hx.data(), n));
+        TRY(upload<float4>(&D.x[1], nullptr, n));
+        TRY(upload(&D.v[0], hv.data(), 3 * n));
+        TRY(upload<float>(&D.v[1], nullptr, 3 * n));
+        TRY(upload(&D.mass, hm.data(), n));
+        if (d->fext) TRY(upload(&D.fext, hf.data(), 3 * n));
+        TRY(upload(&D.slice_ptr, L.slice_ptr.data(), L.slice_ptr.size()));
+        TRY(upload(&D.nbr, L.nbr_local.data(), entries));
+        TRY(upload(&D.kl, hkl.data(), entries));
+        if (sim->actuated) TRY(upload(&D.grp, hg.data(), entries));
+        TRY(upload(&D.halo_ptr, L.halo_ptr.data(), L.halo_ptr.size()));
+        TRY(upload(&D.halo_idx, L.halo_idx.data(), L.halo_idx.size()));
+        std::vector<float> ones(n_factor + 1, 1.0f);
+        std::vector<double> zeros(std::max<int32_t>(n_factor, 1), 0.0);
+        TRY(upload(&D.factor, ones.data(), ones.size()));
+        TRY(upload(&D.phase, zeros.data(), zeros.size()));
+        TRY(upload(&D.amp, zeros.data(), zeros.size()));
+        long long zero = 0;
+        TRY(upload(&D.step_ctr, &zero, 1));
+        TRY(upload(&D.chunks, chunks.data(), chunks.size()));
+        TRY(upload(&D.body_chunk, body_chunk.data(), body_chunk.size()));
+        TRY(upload<double>(&D.chunk_part, nullptr, chunks.size() * cronos::kDiagFields));
+        TRY(upload<double>(&D.body_out, nullptr, (size_t)sim->nb * cronos::kDiagFields));
+        TRY(upload<float>(&D.fout, nullptr, 3 * n));
+        HIP_TRY(hipDeviceSynchronize());
+        return CRONOS_OK;
+    }();
+    if (st != CRONOS_OK) {
+        free_device(sim);
+        delete sim;
+        return st;
+    }
+    cronos::StepParams& P = sim->p;
+    P.dt = (float)d->dt;
+    P.damp = (float)(1.0 - d->damping);
+    P.gx = (float)d->gravity[0];
+    P.gy = (float)d->gravity[1];
+    P.gz = (float)d->gravity[2];
+    P.ground = d->ground ? 1 : 0;
+    P.ground_z = (float)d->ground_z;
+    P.ground_k = (float)d->ground_k;
+    P.ground_mu = (float)d->ground_mu;
+    P.exact = (d->flags & CRONOS_FAST_DIFF) ? 0 : 1;
+    // the Morton-order host copies are only needed at creation
+    sim->lay.nbr_local.clear();
+    sim->lay.nbr_local.shrink_to_fit();
+    sim->lay.entry_csr.clear();
+    sim->lay.entry_csr.shrink_to_fit();
+    *out = sim;
+    return CRONOS_OK;
+}
+
+extern "C" void cronos_destroy(cronos_sim sim) {
+    if (!sim) return;
+    (void)hipSetDevice(sim->device);
+    if (sim->stream) (void)hipStreamSynchronize(sim->stream);
+    free_device(sim);
+    delete sim;
+}
+
+extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phase, const double* amp, double freq_hz) {
+    cronos::clear_error();
+    if (!sim) return fail(CRONOS_EINVAL, "set_actuation: NULL handle");
+    if (!sim->actuated) return fail(CRONOS_EINVAL, "set_actuation: simulation has no actuation groups");
+    if (!phase || !amp || !std::isfinite(freq_hz)) return fail(CRONOS_EINVAL, "set_actuation: bad arguments");
+    const size_t m = (size_t)sim->d.n_factor;
+    for (size_t g = 0; g < m; ++g)
+        if (!std::isfinite(phase[g]) || !std::isfinite(amp[g])) return fail(CRONOS_EINVAL, "set_actuation: non-finite value");
+    HIP_TRY(hipSetDevice(sim->device));
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    HIP_TRY(hipMemcpy(sim->d.phase, phase, m * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sim->d.amp, amp, m * sizeof(double), hipMemcpyHostToDevice));
+    sim->omega = 2.0 * M_PI * freq_hz;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_step(cronos_sim sim, int64_t n_steps) {
+    cronos::clear_error();
+    if (!sim) return fail(CRONOS_EINVAL, "step: NULL handle");
+    if (n_steps < 0) return fail(CRONOS_EINVAL, "step: n_steps < 0");
+    HIP_TRY(hipSetDevice(sim->device));
+    int64_t left = n_steps;
+    if (sim->use_graph && sim->stream && left >= kGraphSteps) {
+        TRY(ensure_graph(sim));
+        while (left >= kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(sim->graph[sim->cur], sim->stream));
+            left -= kGraphSteps;
+        }
+    }
+    TRY(enqueue_plain(sim, left));
+    sim->step += n_steps;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_read_state(cronos_sim sim, double* x, double* v, int64_t* step) {
+    cronos::clear_error();
+    if (!sim) return fail(CRONOS_EINVAL, "read_state: NULL handle");
+    const int64_t n = sim->d.n;
+    HIP_TRY(hipSetDevice(sim->device));
+    if (!sim->h_x) HIP_TRY(hipHostMalloc((void**)&sim->h_x, n * sizeof(float4), 0));
+    if (!sim->h_v) HIP_TRY(hipHostMalloc((void**)&sim->h_v, 3 * n * sizeof(float), 0));
+    if (x) HIP_TRY(hipMemcpyAsync(sim->h_x, sim->d.x[sim->cur], n * sizeof(float4), hipMemcpyDeviceToHost, sim->stream));
+    if (v) HIP_TRY(hipMemcpyAsync(sim->h_v, sim->d.v[sim->cur], 3 * n * sizeof(float), hipMemcpyDeviceToHost, sim->stream));
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    const cronos::Layout& L = sim->lay;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t o = L.perm[i];
+        if (x) {
+            x[3 * o + 0] = sim->h_x[i].x;
+            x[3 * o + 1] = sim->h_x[i].y;
+            x[3 * o + 2] = sim->h_x[i].z;
+        }
+        if (v)
+            for (int c = 0; c < 3; ++c) v[3 * o + c] = sim->h_v[3 * i + c];
+    }
+    if (step) *step = sim->step;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_set_state(cronos_sim sim, const double* x, const double* v, int64_t step) {
+    cronos::clear_error();
+    if (!sim) return fail(CRONOS_EINVAL, "set_state: NULL handle");
+    if (step < 0) return fail(CRONOS_EINVAL, "set_state: step < 0");
+    const int64_t n = sim->d.n;
+    const cronos::Layout& L = sim->lay;
+    HIP_TRY(hipSetDevice(sim->device));
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    if (x) {
+        std::vector<float4> hx(n);
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t o = L.perm[i];
+            for (int c = 0; c < 3; ++c)
+                if (!std::isfinite(x[3 * o + c])) return fail(CRONOS_EINVAL, "set_state: non-finite x");
+            hx[i] = make_float4((float)x[3 * o], (float)x[3 * o + 1], (float)x[3 * o + 2], sim->inv_m[i]);
+        }
+        HIP_TRY(hipMemcpy(sim->d.x[sim->cur], hx.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    }
+    if (v) {
+        std::vector<float> hv(3 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t o = L.perm[i];
+            for (int c = 0; c < 3; ++c) hv[3 * i + c] = sim->inv_m[i] == 0.0f ? 0.0f : (float)v[3 * o + c];
+        }
+        HIP_TRY(hipMemcpy(sim->d.v[sim->cur], hv.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice));
+    }
+    long long ctr = step;
+    HIP_TRY(hipMemcpy(sim->d.step_ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice));
+    sim->step = step;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_eval_forces(cronos_sim sim, double* f) {
+    cronos::clear_error();
+    if (!sim || !f) return fail(CRONOS_EINVAL, "eval_forces: NULL argument");
+    const int64_t n = sim->d.n;
+    HIP_TRY(hipSetDevice(sim->device));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->omega, sim->dt, 0, sim->stream));
+    HIP_TRY(cronos::launch_forces(sim->d, sim->cur, sim->p, sim->stream));
+    if (!sim->h_f) HIP_TRY(hipHostMalloc((void**)&sim->h_f, 3 * n * sizeof(float), 0));
+    HIP_TRY(hipMemcpyAsync(sim->h_f, sim->d.fout, 3 * n * sizeof(float), hipMemcpyDeviceToHost, sim->stream));
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t o = sim->lay.perm[i];
+        for (int c = 0; c < 3; ++c) f[3 * o + c] = sim->h_f[3 * i + c];
+    }
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out) {
+    cronos::clear_error();
+    if (!sim || !out) return fail(CRONOS_EINVAL, "diagnostics: NULL argument");
+    HIP_TRY(hipSetDevice(sim->device));
+    const int nb = sim->nb;
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->omega, sim->dt, 0, sim->stream));
+    HIP_TRY(cronos::launch_diagnostics(sim->d, sim->cur, sim->p, sim->stream));
+    if (!sim->h_diag) HIP_TRY(hipHostMalloc((void**)&sim->h_diag, (size_t)nb * cronos::kDiagFields * sizeof(double), 0));
+    HIP_TRY(hipMemcpyAsync(sim->h_diag, sim->d.body_out, (size_t)nb * cronos::kDiagFields * sizeof(double),
+                           hipMemcpyDeviceToHost, sim->stream));
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    bool bad = false;
+    for (int b = 0; b < nb; ++b) {
+        const double* q = sim->h_diag + (size_t)b * cronos::kDiagFields;
+        cronos_diag& o = out[b];
+        std::memset(&o, 0, sizeof o);
+        o.ke = q[0];
+        o.pe_spring = q[1];
+        o.pe_grav = q[2];
+        o.pe_contact = q[3];
+        o.mass = q[10];
+        for (int c = 0; c < 3; ++c) {
+            o.p[c] = q[4 + c];
+            o.com[c] = q[7 + c] / q[10];
+            o.bbox_max[c] = q[11 + c];
+            o.bbox_min[c] = q[14 + c];
+        }
+        o.step = sim->step;
+        o.nonfinite = q[17] > 0.0 || !std::isfinite(q[0]) || !std::isfinite(q[1]);
+        bad = bad || o.nonfinite;
+    }
+    if (bad) return fail(CRONOS_ESTATE, "diagnostics: non-finite state");
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
+                                     int32_t* block_masses, int64_t* step) {
+    if (!sim) return fail(CRONOS_EINVAL, "info: NULL handle");
+    if (n_masses) *n_masses = sim->lay.n;
+    if (n_springs) *n_springs = sim->lay.s;
+    if (n_bodies) *n_bodies = sim->nb;
+    if (block_masses) *block_masses = sim->lay.block;
+    if (step) *step = sim->step;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_get_layout(cronos_sim sim, int32_t* perm, int64_t* row_ptr, int32_t* col,
+                                           int32_t* sid, int32_t* spring_perm) {
+    if (!sim) return fail(CRONOS_EINVAL, "get_layout: NULL handle");
+    const cronos::Layout& L = sim->lay;
+    if (perm) std::memcpy(perm, L.perm.data(), L.n * sizeof(int32_t));
+    if (row_ptr) std::memcpy(row_ptr, L.row_ptr.data(), (L.n + 1) * sizeof(int64_t));
+    if (col) std::memcpy(col, L.col.data(), 2 * L.s * sizeof(int32_t));
+    if (sid) std::memcpy(sid, L.sid.data(), 2 * L.s * sizeof(int32_t));
+    if (spring_perm) std::memcpy(spring_perm, L.spring_perm.data(), L.s * sizeof(int32_t));
+    return CRONOS_OK;
+}
