@@ -4,8 +4,11 @@ fraction and the FP64 oracle timed on the host as a reported CPU baseline.
 Workload (default): the cantilever beam of 400 x 40 x 40 nodes (640,000 masses, 8,020,476
 springs, 0.005 m spacing, per-voxel stiffness for E = 1 MPa, one end face fixed, gravity on,
 no ground, dt = 5e-5 s), synthetic and seeded.  One step = one time step of the whole body.
+``--workload population``: 1024 random-walk robots (node targets log-uniform in [500, 50k],
+3 materials, 32 actuation groups each, contact plane, dt = 1e-4 s) stepped together, one
+launch per step; also reports rollouts/s for the 5000-step rollout.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload W] [--tune]
 
 Prints ONE JSON line.  Timing: W untimed steps, then exactly K steps bracketed by
 torch.cuda.synchronize() and HIP events recorded on the stream the library launches on.
@@ -62,6 +65,12 @@ def cpu_baseline(workload, steps: int):
     from oracle import lattice as L
     from oracle import physics as P
 
+    if len(workload.bodies) > 8:      # a bounded sample: the first 8 robots of the population
+        import dataclasses
+        G = workload.n_groups
+        workload = dataclasses.replace(workload, name=workload.name + "[first 8 robots]",
+                                       bodies=workload.bodies[:8], phase=workload.phase[:8 * G],
+                                       amp=workload.amp[:8 * G])
     lat = L.build(workload)
     sys_ = P.system_from(lat, workload)
     x, v = lat.x.copy(), np.zeros_like(lat.x)
@@ -85,6 +94,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
+    ap.add_argument("--workload", choices=("cantilever", "population"), default="cantilever")
+    ap.add_argument("--robots", type=int, default=1024)
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (read MIB, write MIB) before the "
                          "timed steps, as the reference kernel for the HBM byte counters")
@@ -101,13 +113,20 @@ def main():
     from paper_2207_09334_amd import cronos as CR
     from paper_2207_09334_amd import problem as PR
 
-    w = W.cantilever(args.nx, 40, 40)
+    if args.workload == "population":
+        w = W.population(args.robots)
+    else:
+        w = W.cantilever(args.nx, 40, 40)
     lat = PR.build_lattice(w)
     stream = torch.cuda.Stream()
     flags = (CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0)
-    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block)
+    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
+                          tune_steps=20 if args.tune else 0)
     info = CR.cronos_info(sim)
+    launch = CR.cronos_launch_config(sim)
     N, S = info["n_masses"], info["n_springs"]
+    batched = len(w.bodies) > 1
+    actuated = w.n_groups > 0
 
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy * (1 << 18), dtype=torch.float32, device="cuda")
@@ -136,20 +155,24 @@ def main():
 
     sec_per_step = ms / 1e3 / args.steps
     value = S / sec_per_step
-    b_step = algorithmic_bytes(N, S)
+    b_step = algorithmic_bytes(N, S, actuated=actuated, batched=batched)
     achieved = b_step / sec_per_step / 1e9
     traffic = measured_traffic()
     out = {
         "metric": METRIC, "value": value, "unit": "spring-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "n_masses": N, "n_springs": S, "dt": w.dt,
-                   "block_masses": info["block_masses"], "hip_graph": not args.no_graph,
+        "config": {"workload": w.name, "n_bodies": len(w.bodies), "n_masses": N, "n_springs": S, "dt": w.dt,
+                   "block_masses": launch["block_masses"], "batch": launch["batch"],
+                   "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
                    "exact_difference": not args.fast_diff},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": b_step},
     }
+    if batched:
+        out["rollouts_per_s"] = len(w.bodies) / (w.steps * sec_per_step)
+        out["rollout_steps"] = w.steps
     sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

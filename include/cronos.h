@@ -168,7 +168,14 @@ typedef struct {
     int32_t device;               /* HIP device ordinal                                        */
     void* stream;                 /* hipStream_t to enqueue on; NULL = a stream of its own    */
     uint32_t flags;               /* CRONOS_* flags                                           */
-    int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = 256 */
+    int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = the
+                                     tuned value for this problem class if one is cached (see
+                                     cronos_autotune), else 256                               */
+    int32_t batch;                /* incidence entries each lane keeps in flight: 2, 4 or 8;
+                                     0 = tuned or 4                                           */
+    int32_t persistent;           /* 1 = one persistent launch per step (a resident grid walks
+                                     the workgroup blocks); 0 = tuned or one workgroup per block;
+                                     -1 = force one workgroup per block                       */
 } cronos_desc;
 
 /* Per-body diagnostics (section "Energy Conservation Tests": elastic, gravitational and
@@ -221,6 +228,45 @@ cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);
 /* Information on the simulation: masses, springs, bodies, groups, steps taken, block size. */
 cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
                           int32_t* block_masses, int64_t* step);
+/* Launch configuration in use: batch, persistent workgroups (0 = one per block). */
+cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups);
+
+/* Launch configuration chosen by the autotuner for a problem. */
+typedef struct {
+    int32_t block_masses, batch, persistent;
+    double us_per_step;           /* measured mean step time of the winner                     */
+    double us_default;            /* same for block 256, batch 4, one workgroup per block      */
+} cronos_tune;
+
+/* Autotuner (not in the paper; the step's launch shape).  Creates the simulation of desc
+ * once per workgroup size in {128, 256, 512, 1024} and times n_steps steps (after 3 warm-up
+ * steps, HIP events on its stream) for every batch in {2, 4, 8} and both launch forms; the
+ * fastest configuration is returned and cached for the process under the key (GPU
+ * architecture, floor(log2 N), floor(log2 S), actuated, contact), and appended to the file
+ * named by the environment variable CRONOS_TUNE_CACHE if set (read back at the first
+ * cronos_create).  The state of desc is not modified.  Errors: as cronos_create. */
+cronos_status cronos_autotune(const cronos_desc* desc, int32_t n_steps, cronos_tune* out);
+
+/* ------------------------------------------------------------------------------------------
+ * Differentiable rollouts (the paper notes differentiation is enabled by its system without
+ * describing it; this is the reverse-mode adjoint of the discrete step above).
+ * ---------------------------------------------------------------------------------------- */
+
+/* Run n_steps steps from the current state (as cronos_step), saving the state every
+ * ckpt_every steps on the device, and return loss = sum_i loss_w[i] . x_i(T) in FP64
+ * (loss_w: host [N][3], input order, rounded to FP32 for the adjoint).  Blocking.  The
+ * rollout is recorded for cronos_rollout_backward until the next cronos_rollout.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t ckpt_every, const double* loss_w,
+                             double* loss);
+
+/* Gradient of the last rollout's loss: dphase, damp [n_bodies*n_groups] with respect to the
+ * actuation phases and amplitudes, dx0, dv0 [N][3] with respect to the state the rollout
+ * started from (input order).  Any output may be NULL.  Each checkpointed segment is
+ * recomputed forward, then stepped backwards with the adjoint kernels (FP32 adjoint state,
+ * FP64 accumulation of the actuation sensitivities).  Blocking.  Does not change the state.
+ * Errors: EINVAL (no rollout recorded), EDEVICE. */
+cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase, double* damp, double* dx0, double* dv0);
 
 /* Input-order layout of a created simulation (see cronos_layout_get). */
 cronos_status cronos_get_layout(cronos_sim sim, int32_t* perm, int64_t* row_ptr, int32_t* col,

@@ -53,7 +53,13 @@ class Desc(C.Structure):
                 ("ends", _p), ("k", _p), ("rest", _p), ("group", _p), ("n_groups", _i32),
                 ("gravity", _f64 * 3), ("damping", _f64), ("dt", _f64), ("ground", _i32),
                 ("ground_z", _f64), ("ground_k", _f64), ("ground_mu", _f64), ("device", _i32),
-                ("stream", _p), ("flags", _u32), ("block_masses", _i32)]
+                ("stream", _p), ("flags", _u32), ("block_masses", _i32), ("batch", _i32),
+                ("persistent", _i32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("block_masses", _i32), ("batch", _i32), ("persistent", _i32), ("us_per_step", _f64),
+                ("us_default", _f64)]
 
 
 class Diag(C.Structure):
@@ -91,6 +97,10 @@ _SIGS = {
     "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
                               C.POINTER(_i64)]),
     "cronos_get_layout": (C.c_int, [_p] * 6),
+    "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
+    "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
+    "cronos_rollout_backward": (C.c_int, [_p, _p, _p, _p, _p]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -227,7 +237,7 @@ class Sim:
 def cronos_create(x0, mass, ends, k, rest, *, v0=None, pinned=None, grid=None, fext=None, group=None,
                   n_groups=0, body_offset=None, gravity=(0.0, 0.0, -9.81), damping=0.0, dt=1e-4, ground=False,
                   ground_z=0.0, ground_k=0.0, ground_mu=0.0, device=0, stream=None, flags=0,
-                  block_masses=0) -> Sim:
+                  block_masses=0, batch=0, persistent=0, _tune_steps=0):
     x0 = _arr(x0, np.float64, (-1, 3))
     n = len(x0)
     ends = _arr(ends, np.int32, (-1, 2))
@@ -242,10 +252,27 @@ def cronos_create(x0, mass, ends, k, rest, *, v0=None, pinned=None, grid=None, f
              rest=_ptr(keep["rest"]), group=_ptr(keep["group"]), n_groups=n_groups,
              gravity=(_f64 * 3)(*gravity), damping=damping, dt=dt, ground=int(bool(ground)), ground_z=ground_z,
              ground_k=ground_k, ground_mu=ground_mu, device=device, stream=stream, flags=flags,
-             block_masses=block_masses)
+             block_masses=block_masses, batch=batch, persistent=persistent)
+    if _tune_steps:
+        t = Tune()
+        _check(_lib.cronos_autotune(C.byref(d), int(_tune_steps), C.byref(t)))
+        return {"block_masses": t.block_masses, "batch": t.batch, "persistent": t.persistent,
+                "us_per_step": t.us_per_step, "us_default": t.us_default}
     h = _p()
     _check(_lib.cronos_create(C.byref(d), C.byref(h)))
     return Sim(h, n, len(ends), nb, n_groups)
+
+
+def cronos_autotune(x0, mass, ends, k, rest, n_steps=20, **kw) -> dict:
+    """Same arguments as cronos_create; returns the tuned launch configuration (and caches it
+    in the library for later creates of the same problem class)."""
+    return cronos_create(x0, mass, ends, k, rest, _tune_steps=n_steps, **kw)
+
+
+def cronos_launch_config(sim: Sim) -> dict:
+    b, bt, pg = _i32(), _i32(), _i32()
+    _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg)))
+    return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value}
 
 
 def cronos_destroy(sim: Sim):
@@ -305,3 +332,22 @@ def cronos_get_layout(sim: Sim) -> dict:
     _check(_lib.cronos_get_layout(sim.handle, *[_ptr(out[f]) for f in ("perm", "row_ptr", "col", "sid",
                                                                        "spring_perm")]))
     return out
+
+
+def cronos_rollout(sim: Sim, n_steps: int, ckpt_every: int, loss_w) -> float:
+    lw = _arr(loss_w, np.float64, (-1, 3))
+    if len(lw) != sim.n_masses:
+        raise CronosError(EINVAL, "loss_w must have n_masses rows")
+    out = _f64()
+    _check(_lib.cronos_rollout(sim.handle, int(n_steps), int(ckpt_every), _ptr(lw), C.byref(out)))
+    return out.value
+
+
+def cronos_rollout_backward(sim: Sim, want_state=False):
+    """Returns (dphase, damp) or, with want_state, (dphase, damp, dx0, dv0)."""
+    G = sim.n_bodies * sim.n_groups
+    dp, da = np.zeros(G), np.zeros(G)
+    dx = np.empty((sim.n_masses, 3)) if want_state else None
+    dv = np.empty((sim.n_masses, 3)) if want_state else None
+    _check(_lib.cronos_rollout_backward(sim.handle, _ptr(dp), _ptr(da), _ptr(dx), _ptr(dv)))
+    return (dp, da, dx, dv) if want_state else (dp, da)

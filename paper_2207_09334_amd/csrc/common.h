@@ -1,15 +1,37 @@
 // Internal helpers shared by the host sources of the library (error reporting, sizes).
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstdarg>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "cronos.h"
 
 namespace cronos {
+
+// Runs fn(begin, end) over [0, n) split into contiguous chunks on up to 16 host threads.
+// Each chunk must write only its own outputs, so results do not depend on the thread count.
+template <typename F>
+void parallel_for(int64_t n, F fn, int64_t min_chunk = 1024) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t t = std::min<int64_t>(hw ? hw : 1, 16);
+    t = std::min<int64_t>(t, (n + min_chunk - 1) / min_chunk);
+    if (t <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + t - 1) / t;
+    for (int64_t k = 0; k < t; ++k) {
+        int64_t b = k * chunk, e = std::min<int64_t>(n, b + chunk);
+        if (b < e) th.emplace_back(fn, b, e);
+    }
+    for (auto& x : th) x.join();
+}
 
 // Sets the calling thread's last-error text and returns the status.
 cronos_status fail(cronos_status st, const char* fmt, ...);
@@ -33,11 +55,15 @@ struct Layout {
     std::vector<int64_t> row_ptr;       // [N+1]
     std::vector<int32_t> col, sid;      // [2S]
 
-    // sliced layout: slice s covers new masses [64 s, 64 s + 64); workgroup b covers
-    // [b*block, (b+1)*block) and stages its masses plus its halo in LDS.
+    // sliced layout: workgroup b covers masses [b*block, (b+1)*block) and stages their
+    // positions plus its halo in LDS; lane t of the workgroup owns mass b*block +
+    // lane_mass[b*block + t]; slice s covers lanes [64 s, 64 s + 64).
     int32_t block = kDefaultBlock;
     int64_t nblk = 0, nslice = 0;
-    std::vector<int32_t> slice_ptr;     // [nslice+1] first entry of each slice
+    std::vector<uint16_t> lane_mass;    // [nblk*block] mass (offset from the block base) each lane
+                                        // owns: a block's masses sorted by decreasing degree, so
+                                        // a 64-lane slice holds masses of similar degree
+    std::vector<int32_t> slice_ptr;     // [nslice+1] first entry of each slice (slices = lanes)
     std::vector<uint16_t> nbr_local;    // [entries] LDS slot of the neighbour
     std::vector<int32_t> entry_csr;     // [entries] CSR position, -1 = padding
     std::vector<int32_t> halo_ptr;      // [nblk+1]

@@ -20,11 +20,15 @@ struct DeviceArrays {
     int64_t n = 0;          // masses
     int32_t block = 256;    // masses (= threads) per workgroup
     int64_t nblk = 0;
+    int64_t nslice = 0;     // nblk * block / 64
     int32_t lds_slots = 0;  // block + largest halo
+    int32_t batch = 4;      // incidence entries fetched per batch (2, 4 or 8)
+    int32_t persistent_groups = 0;  // > 0: persistent grid of that many workgroups
     float4* x[2] = {nullptr, nullptr};   // (x, y, z, 1/m); 1/m = 0 marks a fixed mass
     float* v[2] = {nullptr, nullptr};    // [n][3]
     float* mass = nullptr;               // [n]
     float* fext = nullptr;               // [n][3] or null
+    uint16_t* lane_mass = nullptr;       // [nblk*block] mass owned by each lane, block-relative
     int32_t* slice_ptr = nullptr;
     uint16_t* nbr = nullptr;
     float2* kl = nullptr;                // (k, L0) per entry
@@ -50,7 +54,20 @@ struct DeviceArrays {
 constexpr int kDiagFields = 20;  // ke, pe_s, pe_g, pe_c, p3, mx3, mass, min3, max3, nonfinite
 
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
-hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st);
+// The step with explicit buffers; vstar (optional) receives the velocity before friction/damping.
+hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
+                          float* vstar, const StepParams& p, hipStream_t st);
+// Workgroups of a persistent launch that are resident at once on the device (multiple of 8).
+hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid);
+// Actuation table for the device step counter (advancing it when advance != 0), or for the
+// explicit step n_explicit >= 0 (counter untouched).
+hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st,
+                            long long n_explicit = -1);
+// Adjoint of one step (see kernels.hip).
+hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,
+                            const float* vb1, float4* w, float* vb0, float* xbl, const StepParams& p, hipStream_t st);
+hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
+                             double2* sens, double cos_t, double sin_t, hipStream_t st);
 hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 hipError_t launch_diagnostics(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 

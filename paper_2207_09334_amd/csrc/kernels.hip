@@ -19,6 +19,8 @@
 // TwoSum), so its error is a few ulps of the elongation itself, not of L0.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace cronos {
@@ -87,28 +89,28 @@ __device__ __forceinline__ void hooke(float xi, float yi, float zi, float xj, fl
     fz = __builtin_fmaf(fac, dz, fz);
 }
 
-// Stage the workgroup's own positions and its halo in LDS.  Returns this lane's position.
-__device__ __forceinline__ float4 stage_positions(float4* __restrict__ sx, const float4* __restrict__ xin,
-                                                  const int32_t* __restrict__ halo_ptr,
-                                                  const int32_t* __restrict__ halo_idx, int b, int base,
-                                                  int n, int block) {
+// Stage the workgroup's masses (in mass order) and its halo in LDS; returns the block-relative
+// index of the mass this lane owns (lanes take the block's masses by decreasing degree).
+__device__ __forceinline__ int stage_positions(float4* __restrict__ sx, const float4* __restrict__ xin,
+                                               const int32_t* __restrict__ halo_ptr,
+                                               const int32_t* __restrict__ halo_idx,
+                                               const uint16_t* __restrict__ lane_mass, int b, int base, int n,
+                                               int block) {
     const int t = threadIdx.x;
-    const int i = base + t;
-    float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < n) xi = xin[i];
-    sx[t] = xi;
+    const int own = lane_mass[base + t];
+    float4 xt = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (base + t < n) xt = xin[base + t];
+    sx[t] = xt;
     const int h0 = halo_ptr[b], h1 = halo_ptr[b + 1];
     for (int h = h0 + t; h < h1; h += block) sx[block + (h - h0)] = xin[halo_idx[h]];
     __syncthreads();
-    return xi;
+    return own;
 }
 
 // Sum of the spring forces on this lane's mass over its slice entries.  The slice (and so the
-// trip count) is uniform across the wavefront; entries are fetched in batches of kBatch so
+// trip count) is uniform across the wavefront; entries are fetched in batches of BATCH so
 // that several loads are in flight before the first is consumed.
-constexpr int kBatch = 4;
-
-template <bool ACT, bool EXACT>
+template <bool ACT, bool EXACT, int BATCH>
 __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi, int s, int nslice,
                                        const int32_t* __restrict__ slice_ptr,
                                        const uint16_t* __restrict__ nbr, const float2* __restrict__ kl,
@@ -124,18 +126,18 @@ __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi,
     const float2* pk = kl + e0 + lane;
     const uint16_t* pg = ACT ? grp + e0 + lane : nullptr;
     int r = 0;
-    for (; r + kBatch <= w; r += kBatch) {
-        int slot[kBatch];
-        float2 c[kBatch];
-        float f[kBatch];
+    for (; r + BATCH <= w; r += BATCH) {
+        int slot[BATCH];
+        float2 c[BATCH];
+        float f[BATCH];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
             slot[u] = pn[(r + u) * 64];
             c[u] = pk[(r + u) * 64];
             if (ACT) f[u] = factor[pg[(r + u) * 64]];
         }
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
             const float4 xj = sx[slot[u]];
             const float l0 = ACT ? c[u].y * f[u] : c[u].y;
             hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c[u].x, l0, fx, fy, fz);
@@ -150,36 +152,49 @@ __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi,
     }
 }
 
-template <bool ACT, bool GROUND, bool FEXT, bool EXACT>
-__global__ void __launch_bounds__(1024)
-step_kernel(const float4* __restrict__ xin, const float* __restrict__ vin, float4* __restrict__ xout,
-            float* __restrict__ vout, const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
-            const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
-            const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
-            const float* __restrict__ factor, const float* __restrict__ fext, int n, int nblk, int nslice,
-            int block, StepParams p) {
-    extern __shared__ float4 sx[];
-    const int b = logical_block(nblk);
-    if (b >= nblk) return;
-    const int base = b * block;
-    const float4 xi = stage_positions(sx, xin, halo_ptr, halo_idx, b, base, n, block);
+struct StepArgs {
+    const float4* __restrict__ xin;
+    const float* __restrict__ vin;
+    float4* __restrict__ xout;
+    float* __restrict__ vout;
+    const int32_t* __restrict__ slice_ptr;
+    const uint16_t* __restrict__ nbr;
+    const float2* __restrict__ kl;
+    const uint16_t* __restrict__ grp;
+    const int32_t* __restrict__ halo_ptr;
+    const int32_t* __restrict__ halo_idx;
+    const uint16_t* __restrict__ lane_mass;
+    const float* __restrict__ factor;
+    const float* __restrict__ fext;
+    float* __restrict__ vstar_out;   // optional: velocity before friction and damping (adjoint recompute)
+    int n, nblk, nslice, block;
+};
+
+// One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
+// damping, symplectic Euler, fixed masses.
+template <bool ACT, bool EXACT, int BATCH>
+__device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b) {
+    const int base = b * a.block;
+    const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
+    const float4 xi = sx[own];
     float fx, fy, fz;
-    gather<ACT, EXACT>(sx, xi, (base + (int)threadIdx.x) >> 6, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
-    const int i = base + (int)threadIdx.x;
-    if (i >= n) return;
+    gather<ACT, EXACT, BATCH>(sx, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp,
+                              a.factor, fx, fy, fz);
+    const int i = base + own;
+    if (i >= a.n) return;
 
     const float inv_m = xi.w;
-    float vx = vin[3 * i + 0], vy = vin[3 * i + 1], vz = vin[3 * i + 2];
+    float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
     float ax = __builtin_fmaf(fx, inv_m, p.gx);
     float ay = __builtin_fmaf(fy, inv_m, p.gy);
     float az = __builtin_fmaf(fz, inv_m, p.gz);
-    if (FEXT) {
-        ax = __builtin_fmaf(fext[3 * i + 0], inv_m, ax);
-        ay = __builtin_fmaf(fext[3 * i + 1], inv_m, ay);
-        az = __builtin_fmaf(fext[3 * i + 2], inv_m, az);
+    if (a.fext) {
+        ax = __builtin_fmaf(a.fext[3 * i + 0], inv_m, ax);
+        ay = __builtin_fmaf(a.fext[3 * i + 1], inv_m, ay);
+        az = __builtin_fmaf(a.fext[3 * i + 2], inv_m, az);
     }
     float fn = 0.0f;
-    if (GROUND) {
+    if (p.ground) {
         const float pen = p.ground_z - xi.z;
         fn = pen > 0.0f ? p.ground_k * pen : 0.0f;
         az = __builtin_fmaf(fn, inv_m, az);
@@ -187,7 +202,12 @@ step_kernel(const float4* __restrict__ xin, const float* __restrict__ vin, float
     vx = __builtin_fmaf(p.dt, ax, vx);
     vy = __builtin_fmaf(p.dt, ay, vy);
     vz = __builtin_fmaf(p.dt, az, vz);
-    if (GROUND && fn > 0.0f) {
+    if (a.vstar_out) {
+        a.vstar_out[3 * i + 0] = vx;
+        a.vstar_out[3 * i + 1] = vy;
+        a.vstar_out[3 * i + 2] = vz;
+    }
+    if (fn > 0.0f) {
         // Coulomb clamp: the tangential speed loses mu F_n dt / m, or stops
         const float c = p.ground_mu * fn * p.dt * inv_m;
         const float sp = __builtin_sqrtf(vx * vx + vy * vy);
@@ -207,10 +227,35 @@ step_kernel(const float4* __restrict__ xin, const float* __restrict__ vin, float
         nz = xi.z;
         vx = vy = vz = 0.0f;
     }
-    xout[i] = make_float4(nx, ny, nz, inv_m);
-    vout[3 * i + 0] = vx;
-    vout[3 * i + 1] = vy;
-    vout[3 * i + 2] = vz;
+    a.xout[i] = make_float4(nx, ny, nz, inv_m);
+    a.vout[3 * i + 0] = vx;
+    a.vout[3 * i + 1] = vy;
+    a.vout[3 * i + 2] = vz;
+}
+
+// One workgroup per block.
+template <bool ACT, bool EXACT, int BATCH>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
+    extern __shared__ float4 sx[];
+    const int b = logical_block(a.nblk);
+    if (b >= a.nblk) return;
+    step_block<ACT, EXACT, BATCH>(sx, a, p, b);
+}
+
+// Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
+// on XCD w % 8 and takes that XCD's contiguous eighth of the blocks in strides.
+template <bool ACT, bool EXACT, int BATCH>
+__global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p) {
+    extern __shared__ float4 sx[];
+    const int per = (a.nblk + 7) >> 3;
+    const int xcd = (int)(blockIdx.x & 7u);
+    const int stride = (int)(gridDim.x >> 3);
+    for (int j = (int)(blockIdx.x >> 3); j < per; j += stride) {
+        const int b = xcd * per + j;
+        if (b >= a.nblk) break;
+        step_block<ACT, EXACT, BATCH>(sx, a, p, b);
+        __syncthreads();  // LDS is restaged for the next block
+    }
 }
 
 // Total force of eq. (2) + contact normal at the current state (same gather as the step).
@@ -219,16 +264,18 @@ __global__ void __launch_bounds__(1024)
 forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, const int32_t* __restrict__ slice_ptr,
               const uint16_t* __restrict__ nbr, const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
               const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
-              const float* __restrict__ factor, const float* __restrict__ fext, float* __restrict__ fout, int n,
-              int nblk, int nslice, int block, StepParams p) {
+              const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
+              const float* __restrict__ fext, float* __restrict__ fout, int n, int nblk, int nslice, int block,
+              StepParams p) {
     extern __shared__ float4 sx[];
     const int b = logical_block(nblk);
     if (b >= nblk) return;
     const int base = b * block;
-    const float4 xi = stage_positions(sx, xin, halo_ptr, halo_idx, b, base, n, block);
+    const int own = stage_positions(sx, xin, halo_ptr, halo_idx, lane_mass, b, base, n, block);
+    const float4 xi = sx[own];
     float fx, fy, fz;
-    gather<ACT, true>(sx, xi, (base + (int)threadIdx.x) >> 6, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
-    const int i = base + (int)threadIdx.x;
+    gather<ACT, true, 4>(sx, xi, (base + (int)threadIdx.x) >> 6, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    const int i = base + own;
     if (i >= n) return;
     const float m = mass[i];
     fx = __builtin_fmaf(m, p.gx, fx);
@@ -254,8 +301,9 @@ forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, co
 // Launched as ONE workgroup, so the counter update cannot race with its reads.
 __global__ void __launch_bounds__(1024)
 actuation_kernel(const double* __restrict__ phase, const double* __restrict__ amp, double omega, double dt,
-                 long long* __restrict__ step_ctr, float* __restrict__ factor, int n_factor, int advance) {
-    const long long n = *step_ctr;
+                 long long* __restrict__ step_ctr, float* __restrict__ factor, int n_factor, int advance,
+                 long long n_explicit) {
+    const long long n = n_explicit >= 0 ? n_explicit : *step_ctr;
     const double t = (double)n * dt;
     for (int g = threadIdx.x; g < n_factor; g += blockDim.x)
         factor[g] = (float)(1.0 + amp[g] * sin(omega * t + phase[g]));
@@ -288,15 +336,17 @@ diag_chunk_kernel(const float4* __restrict__ xin, const float* __restrict__ vin,
                   const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
                   const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
                   const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
-                  const float* __restrict__ factor, const int4* __restrict__ chunks, double* __restrict__ part,
-                  int n, int nslice, int block, StepParams p) {
+                  const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
+                  const int4* __restrict__ chunks, double* __restrict__ part, int n, int nslice, int block,
+                  StepParams p) {
     extern __shared__ float4 sx[];
     __shared__ double red[16][kDiagFields];
     const int4 ch = chunks[blockIdx.x];
     const int b = ch.x, base = b * block;
-    const float4 xi = stage_positions(sx, xin, halo_ptr, halo_idx, b, base, n, block);
+    const int own = stage_positions(sx, xin, halo_ptr, halo_idx, lane_mass, b, base, n, block);
+    const float4 xi = sx[own];
     const int t = threadIdx.x;
-    const int i = base + t;
+    const int i = base + own;
     const bool mine = i >= ch.y && i < ch.z;
     // fields: 0 ke, 1 pe_spring, 2 pe_grav, 3 pe_contact, 4-6 momentum, 7-9 sum m x,
     //         10 mass, 11-13 bbox max, 14-16 bbox min, 17 non-finite count
@@ -323,7 +373,7 @@ diag_chunk_kernel(const float4* __restrict__ xin, const float* __restrict__ vin,
         const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz);
         acc[17] = fin ? 0.0 : 1.0;
         // spring energy of springs whose other end has a larger index
-        const int s = i >> 6;
+        const int s = (base + t) >> 6;
         if (s < nslice) {
             const int lane = t & 63;
             const int e0 = slice_ptr[s];
@@ -387,75 +437,255 @@ __global__ void diag_body_kernel(const double* __restrict__ part, const int32_t*
     for (int f = 0; f < 18; ++f) d[f] = o[f];
 }
 
+// ---------------------------------------------------------------- adjoint of one step
+//
+// For the loss L = sum_i w_i . x_i(T), with (x_bar', v_bar') the adjoints of the outputs of
+// step n, the reverse of the step is (see the step above, in reverse order):
+//   v'_bar_tot = v_bar' + dt x_bar'          (x' = x + dt v')
+//   v**_bar    = (1 - d) v'_bar_tot          (damping)
+//   v*_bar     = J^T v**_bar                 (friction clamp: J = I - (c/|v_t|)(I - u u^T) on
+//                                             the tangential part when sliding, 0 when stuck)
+//   c_bar      = -u . v**_bar_t,  c = mu k_g (z_g - z) dt / m  ->  z_bar += c_bar (-mu k_g dt / m)
+//   w          = dt v*_bar / m               (adjoint of the force on the mass)
+//   x_bar      = x_bar' - k_g w_z (contact) + sum_springs K_s (w_j - w_i)
+//   K_s        = k [n n^T + (delta / l)(I - n n^T)]
+//   theta_bar += (dL0/dtheta) k n . (w_j - w_i)   (actuated springs)
+// Fixed masses (1/m = 0) have w = 0 and v_bar = 0.  adj_local computes everything but the
+// spring sum; adj_gather adds the spring sum with the same LDS-staged incidence walk as the
+// step, and accumulates each actuated spring's sensitivity in FP64, half from each end.
+
+__global__ void __launch_bounds__(256)
+adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, const float* __restrict__ xb1,
+                 const float* __restrict__ vb1, float4* __restrict__ w, float* __restrict__ vb0,
+                 float* __restrict__ xbl, int n, StepParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 xi = x[i];
+    const float inv_m = xi.w;
+    const float tx = __builtin_fmaf(p.dt, xb1[3 * i + 0], vb1[3 * i + 0]);
+    const float ty = __builtin_fmaf(p.dt, xb1[3 * i + 1], vb1[3 * i + 1]);
+    const float tz = __builtin_fmaf(p.dt, xb1[3 * i + 2], vb1[3 * i + 2]);
+    float gx = p.damp * tx, gy = p.damp * ty, gz = p.damp * tz;
+    float zb = 0.0f;
+    float wz_contact = 0.0f;
+    if (inv_m == 0.0f) {
+        w[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        vb0[3 * i + 0] = vb0[3 * i + 1] = vb0[3 * i + 2] = 0.0f;
+        xbl[3 * i + 0] = xb1[3 * i + 0];
+        xbl[3 * i + 1] = xb1[3 * i + 1];
+        xbl[3 * i + 2] = xb1[3 * i + 2];
+        return;
+    }
+    const float pen = p.ground ? p.ground_z - xi.z : 0.0f;
+    const bool touching = pen > 0.0f;
+    if (touching) {
+        const float fn = p.ground_k * pen;
+        const float c = p.ground_mu * fn * p.dt * inv_m;
+        const float vx = vstar[3 * i + 0], vy = vstar[3 * i + 1];
+        const float sp = __builtin_sqrtf(vx * vx + vy * vy);
+        if (sp > c) {
+            const float ux = vx / sp, uy = vy / sp;
+            const float ug = ux * gx + uy * gy;
+            const float r = c / sp;
+            gx = gx - r * (gx - ux * ug);
+            gy = gy - r * (gy - uy * ug);
+            zb = -ug * (-p.ground_mu * p.ground_k * p.dt * inv_m);
+        } else {
+            gx = gy = 0.0f;
+        }
+    }
+    const float wx = p.dt * gx * inv_m, wy = p.dt * gy * inv_m, wz = p.dt * gz * inv_m;
+    if (touching) wz_contact = -p.ground_k * wz;
+    w[i] = make_float4(wx, wy, wz, 0.0f);
+    vb0[3 * i + 0] = gx;
+    vb0[3 * i + 1] = gy;
+    vb0[3 * i + 2] = gz;
+    xbl[3 * i + 0] = xb1[3 * i + 0];
+    xbl[3 * i + 1] = xb1[3 * i + 1];
+    xbl[3 * i + 2] = xb1[3 * i + 2] + wz_contact + zb;
+}
+
+template <bool ACT>
+__global__ void __launch_bounds__(1024)
+adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, const float* __restrict__ xbl,
+                  float* __restrict__ xb0, const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
+                  const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
+                  const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
+                  const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
+                  double2* __restrict__ sens, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
+                  int block, int lds_slots) {
+    extern __shared__ float4 sx[];
+    float4* sw = sx + lds_slots;
+    const int b = logical_block(nblk);
+    if (b >= nblk) return;
+    const int base = b * block;
+    const int t = threadIdx.x;
+    {
+        float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (base + t < n) wt = w[base + t];
+        sw[t] = wt;
+        const int h0 = halo_ptr[b], h1 = halo_ptr[b + 1];
+        for (int h = h0 + t; h < h1; h += block) sw[block + (h - h0)] = w[halo_idx[h]];
+    }
+    const int own = stage_positions(sx, x, halo_ptr, halo_idx, lane_mass, b, base, n, block);
+    const float4 xi = sx[own];
+    const float4 wi = sw[own];
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    const int s = __builtin_amdgcn_readfirstlane((base + t) >> 6);
+    if (s < nslice) {
+        const int lane = t & 63;
+        const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
+        const int wdt = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
+        for (int r = 0; r < wdt; ++r) {
+            const int e = e0 + r * 64 + lane;
+            const int slot = nbr[e];
+            const float2 c = kl[e];
+            const int g = ACT ? (int)grp[e] : n_factor;
+            const float l0 = ACT ? c.y * factor[g] : c.y;
+            const float4 xj = sx[slot];
+            const float4 wj = sw[slot];
+            const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+            const float len2 = dx * dx + dy * dy + dz * dz;
+            if (len2 > 0.0f) {
+                const float len = __builtin_sqrtf(len2);
+                const float il = 1.0f / len;
+                const float nx = dx * il, ny = dy * il, nz = dz * il;
+                const float dwx = wj.x - wi.x, dwy = wj.y - wi.y, dwz = wj.z - wi.z;
+                const float ndw = nx * dwx + ny * dwy + nz * dwz;
+                const float tr = 1.0f - l0 * il;        // delta / l
+                const float k = c.x;
+                ax += k * (nx * ndw + tr * (dwx - nx * ndw));
+                ay += k * (ny * ndw + tr * (dwy - ny * ndw));
+                az += k * (nz * ndw + tr * (dwz - nz * ndw));
+                if (ACT && g < n_factor) {
+                    const double q = 0.5 * (double)c.y * (double)k * (double)ndw;
+                    double2 acc = sens[e];
+                    acc.x += cos_t * q;
+                    acc.y += sin_t * q;
+                    sens[e] = acc;
+                }
+            }
+        }
+    }
+    const int i = base + own;
+    if (i >= n) return;
+    xb0[3 * i + 0] = xbl[3 * i + 0] + ax;
+    xb0[3 * i + 1] = xbl[3 * i + 1] + ay;
+    xb0[3 * i + 2] = xbl[3 * i + 2] + az;
+}
+
 inline int grid_for(int64_t nblk) { return (int)(((nblk + 7) / 8) * 8); }
 
 }  // namespace
 
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st) {
-    const int nslice = (int)((d.n + 63) / 64);
+    return launch_step_io(d, d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], nullptr, p, st);
+}
+
+hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
+                          float* vstar, const StepParams& p, hipStream_t st) {
+    StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
+               d.lane_mass, d.factor, d.fext, vstar, (int)d.n, (int)d.nblk, (int)d.nslice, d.block};
     const size_t lds = (size_t)d.lds_slots * sizeof(float4);
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, d.x[cur], d.v[cur], d.x[cur ^ 1],
-                           d.v[cur ^ 1], d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.factor, d.fext,
-                           (int)d.n, (int)d.nblk, nslice, d.block, p);
+    const bool persistent = d.persistent_groups > 0;
+    const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
+    auto go = [&](auto normal, auto pers) {
+        if (persistent) hipLaunchKernelGGL(pers, grid, dim3(d.block), lds, st, a, p);
+        else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds, st, a, p);
     };
-    const int key = (d.grp ? 8 : 0) | (p.ground ? 4 : 0) | (d.fext ? 2 : 0) | (p.exact ? 1 : 0);
-    switch (key) {
-        case 0: go(step_kernel<false, false, false, false>); break;
-        case 1: go(step_kernel<false, false, false, true>); break;
-        case 2: go(step_kernel<false, false, true, false>); break;
-        case 3: go(step_kernel<false, false, true, true>); break;
-        case 4: go(step_kernel<false, true, false, false>); break;
-        case 5: go(step_kernel<false, true, false, true>); break;
-        case 6: go(step_kernel<false, true, true, false>); break;
-        case 7: go(step_kernel<false, true, true, true>); break;
-        case 8: go(step_kernel<true, false, false, false>); break;
-        case 9: go(step_kernel<true, false, false, true>); break;
-        case 10: go(step_kernel<true, false, true, false>); break;
-        case 11: go(step_kernel<true, false, true, true>); break;
-        case 12: go(step_kernel<true, true, false, false>); break;
-        case 13: go(step_kernel<true, true, false, true>); break;
-        case 14: go(step_kernel<true, true, true, false>); break;
-        default: go(step_kernel<true, true, true, true>); break;
+#define CRONOS_GO(A, E, B) go(step_kernel<A, E, B>, step_persistent<A, E, B>)
+    const bool act = d.grp != nullptr, ex = p.exact != 0;
+    switch (d.batch) {
+        case 2:
+            if (act) ex ? CRONOS_GO(true, true, 2) : CRONOS_GO(true, false, 2);
+            else ex ? CRONOS_GO(false, true, 2) : CRONOS_GO(false, false, 2);
+            break;
+        case 8:
+            if (act) ex ? CRONOS_GO(true, true, 8) : CRONOS_GO(true, false, 8);
+            else ex ? CRONOS_GO(false, true, 8) : CRONOS_GO(false, false, 8);
+            break;
+        default:
+            if (act) ex ? CRONOS_GO(true, true, 4) : CRONOS_GO(true, false, 4);
+            else ex ? CRONOS_GO(false, true, 4) : CRONOS_GO(false, false, 4);
+            break;
     }
+#undef CRONOS_GO
     return hipGetLastError();
 }
 
-hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st) {
+hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)d.lds_slots * sizeof(float4);
+    const void* k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4> : (const void*)step_persistent<true, false, 4>)
+                          : (exact ? (const void*)step_persistent<false, true, 4> : (const void*)step_persistent<false, false, 4>);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, lds);
+    if (e != hipSuccess) return e;
+    int g = std::max(1, per_cu) * cus;
+    g = (g + 7) / 8 * 8;
+    *grid = (int)std::min<int64_t>(g, grid_for(d.nblk));
+    return hipSuccess;
+}
+
+hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st,
+                            long long n_explicit) {
     hipLaunchKernelGGL(actuation_kernel, dim3(1), dim3(1024), 0, st, d.phase, d.amp, omega, dt, d.step_ctr, d.factor,
-                       d.n_factor, advance);
+                       d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
     return hipGetLastError();
 }
 
 hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st) {
-    const int nslice = (int)((d.n + 63) / 64);
+    const int nslice = (int)d.nslice;
     const size_t lds = (size_t)d.lds_slots * sizeof(float4);
     if (d.grp)
         hipLaunchKernelGGL(forces_kernel<true>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, d.x[cur], d.mass,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.factor, d.fext, d.fout, (int)d.n,
-                           (int)d.nblk, nslice, d.block, p);
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, d.fext,
+                           d.fout, (int)d.n, (int)d.nblk, nslice, d.block, p);
     else
         hipLaunchKernelGGL(forces_kernel<false>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, d.x[cur], d.mass,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.factor, d.fext, d.fout, (int)d.n,
-                           (int)d.nblk, nslice, d.block, p);
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, d.fext,
+                           d.fout, (int)d.n, (int)d.nblk, nslice, d.block, p);
     return hipGetLastError();
 }
 
 hipError_t launch_diagnostics(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st) {
-    const int nslice = (int)((d.n + 63) / 64);
+    const int nslice = (int)d.nslice;
     const size_t lds = (size_t)d.lds_slots * sizeof(float4);
     if (d.grp)
         hipLaunchKernelGGL(diag_chunk_kernel<true>, dim3(d.n_chunks), dim3(d.block), lds, st, d.x[cur], d.v[cur],
-                           d.mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.factor, d.chunks,
-                           d.chunk_part, (int)d.n, nslice, d.block, p);
+                           d.mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor,
+                           d.chunks, d.chunk_part, (int)d.n, nslice, d.block, p);
     else
         hipLaunchKernelGGL(diag_chunk_kernel<false>, dim3(d.n_chunks), dim3(d.block), lds, st, d.x[cur], d.v[cur],
-                           d.mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.factor, d.chunks,
-                           d.chunk_part, (int)d.n, nslice, d.block, p);
+                           d.mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor,
+                           d.chunks, d.chunk_part, (int)d.n, nslice, d.block, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(diag_body_kernel, dim3((d.nb + 63) / 64), dim3(64), 0, st, d.chunk_part, d.body_chunk,
                        d.body_out, d.nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,
+                            const float* vb1, float4* w, float* vb0, float* xbl, const StepParams& p, hipStream_t st) {
+    hipLaunchKernelGGL(adj_local_kernel, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, st, x, vstar, xb1, vb1, w,
+                       vb0, xbl, (int)d.n, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
+                             double2* sens, double cos_t, double sin_t, hipStream_t st) {
+    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4);
+    if (d.grp)
+        hipLaunchKernelGGL(adj_gather_kernel<true>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, sens,
+                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
+    else
+        hipLaunchKernelGGL(adj_gather_kernel<false>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, sens,
+                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
     return hipGetLastError();
 }
 

@@ -181,28 +181,41 @@ extern "C" cronos_status cronos_lattice_build(const cronos_lattice_desc* d, cron
         for (int64_t i = 0; i < d->n_voxels; ++i)
             if (d->group[i] < -1 || d->group[i] > 32767) return cronos::fail(CRONOS_EINVAL, "lattice: group out of range");
     }
+    for (int32_t b = 0; b < d->n_bodies; ++b) {
+        int64_t v0 = d->body_voxel_offset ? d->body_voxel_offset[b] : 0;
+        int64_t v1 = d->body_voxel_offset ? d->body_voxel_offset[b + 1] : d->n_voxels;
+        if (v0 < 0 || v1 > d->n_voxels || v1 < v0) return cronos::fail(CRONOS_EINVAL, "lattice: bad body_voxel_offset");
+    }
     auto* lat = new (std::nothrow) cronos_lattice_t;
     if (!lat) return cronos::fail(CRONOS_ENOMEM, "lattice: out of memory");
+    // bodies are independent: build them on several host threads, report the first failure
+    std::vector<cronos_status> status(d->n_bodies, CRONOS_OK);
+    std::vector<std::string> errors(d->n_bodies);
     try {
         lat->bodies.resize(d->n_bodies);
-        for (int32_t b = 0; b < d->n_bodies; ++b) {
-            int64_t v0 = d->body_voxel_offset ? d->body_voxel_offset[b] : 0;
-            int64_t v1 = d->body_voxel_offset ? d->body_voxel_offset[b + 1] : d->n_voxels;
-            if (v0 < 0 || v1 > d->n_voxels || v1 < v0) {
-                delete lat;
-                return cronos::fail(CRONOS_EINVAL, "lattice: bad body_voxel_offset");
+        cronos::parallel_for(d->n_bodies, [&](int64_t b0, int64_t b1) {
+            for (int64_t b = b0; b < b1; ++b) {
+                int64_t v0 = d->body_voxel_offset ? d->body_voxel_offset[b] : 0;
+                int64_t v1 = d->body_voxel_offset ? d->body_voxel_offset[b + 1] : d->n_voxels;
+                try {
+                    status[b] = build_body(*d, v0, v1, lat->bodies[b]);
+                } catch (const std::bad_alloc&) {
+                    status[b] = CRONOS_ENOMEM;
+                }
+                if (status[b] != CRONOS_OK) errors[b] = cronos_last_error();
             }
-            cronos_status st = build_body(*d, v0, v1, lat->bodies[b]);
-            if (st != CRONOS_OK) {
-                delete lat;
-                return st;
-            }
-            lat->n += (int64_t)lat->bodies[b].mass.size();
-            lat->s += (int64_t)lat->bodies[b].k.size();
-        }
+        }, 1);
     } catch (const std::bad_alloc&) {
         delete lat;
         return cronos::fail(CRONOS_ENOMEM, "lattice: out of memory");
+    }
+    for (int32_t b = 0; b < d->n_bodies; ++b) {
+        if (status[b] != CRONOS_OK) {
+            delete lat;
+            return cronos::fail(status[b], "%s (body %d)", errors[b].empty() ? "lattice: out of memory" : errors[b].c_str(), b);
+        }
+        lat->n += (int64_t)lat->bodies[b].mass.size();
+        lat->s += (int64_t)lat->bodies[b].k.size();
     }
     if (lat->n >= (int64_t(1) << 31)) {
         delete lat;

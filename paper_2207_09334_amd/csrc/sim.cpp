@@ -4,8 +4,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 
 #include "common.h"
@@ -48,6 +53,25 @@ constexpr int kGraphSteps = 16;  // steps per captured graph (even: ping-pong pa
 
 }  // namespace
 
+// Device buffers of a differentiable rollout (checkpoints, one recomputed segment, adjoints).
+struct RolloutBuffers {
+    int64_t n0 = 0, T = 0;
+    int32_t K = 0, nseg = 0;
+    bool valid = false;
+    float4* ck_x = nullptr;   // [nseg][N]
+    float* ck_v = nullptr;    // [nseg][3N]
+    float4* seg_x = nullptr;  // [K+1][N]
+    float* seg_v = nullptr;   // [K+1][3N]
+    float* seg_vs = nullptr;  // [K][3N]
+    float* lossw = nullptr;   // [3N]
+    float4* w = nullptr;      // [N]
+    float* xb[2] = {nullptr, nullptr};
+    float* vb[2] = {nullptr, nullptr};
+    float* xbl = nullptr;
+    double2* sens = nullptr;  // [entries]
+    size_t cap_seg = 0, cap_ck = 0;
+};
+
 struct cronos_sim_t {
     cronos::Layout lay;
     cronos::DeviceArrays d;
@@ -62,6 +86,9 @@ struct cronos_sim_t {
     bool actuated = false, use_graph = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::vector<float> inv_m;            // new order
+    std::vector<uint16_t> h_grp;         // per entry factor index (actuated sims), for the adjoint reduction
+    std::vector<double> h_phase, h_amp;  // actuation parameters last set
+    RolloutBuffers ro;
     float4* h_x = nullptr;               // pinned staging
     float* h_v = nullptr;
     float* h_f = nullptr;
@@ -72,13 +99,18 @@ namespace {
 
 void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
-    void* ptrs[] = {d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
+    void* ptrs[] = {d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
                     d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
                     d.body_out, d.fout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& g : s->graph)
         if (g) (void)hipGraphExecDestroy(g);
+    RolloutBuffers& r = s->ro;
+    void* rp[] = {r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w, r.xb[0], r.xb[1], r.vb[0], r.vb[1], r.xbl,
+                  r.sens};
+    for (void* p : rp)
+        if (p) (void)hipFree(p);
     if (s->h_x) (void)hipHostFree(s->h_x);
     if (s->h_v) (void)hipHostFree(s->h_v);
     if (s->h_f) (void)hipHostFree(s->h_f);
@@ -203,6 +235,64 @@ cronos_status ensure_graph(cronos_sim_t* s) {
     return CRONOS_OK;
 }
 
+// ---- autotuner cache: (arch, log2 N, log2 S, actuated, contact) -> launch configuration
+std::mutex g_tune_mu;
+std::map<std::string, cronos_tune> g_tune;
+bool g_tune_loaded = false;
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+std::string tune_key(const cronos_desc& d) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, d.device) != hipSuccess) return std::string();
+    std::ostringstream k;
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    k << arch << "/" << ilog2(d.n_masses) << "/" << ilog2(std::max<int64_t>(d.n_springs, 1)) << "/"
+      << (d.group ? 1 : 0) << "/" << (d.ground ? 1 : 0);
+    return k.str();
+}
+
+void load_tune_cache_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("CRONOS_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    cronos_tune t{};
+    while (f >> key >> t.block_masses >> t.batch >> t.persistent >> t.us_per_step >> t.us_default) g_tune[key] = t;
+}
+
+bool lookup_tune(const std::string& key, cronos_tune* t) {
+    if (key.empty()) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+void store_tune(const std::string& key, const cronos_tune& t) {
+    if (key.empty()) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    g_tune[key] = t;
+    if (const char* path = std::getenv("CRONOS_TUNE_CACHE")) {
+        std::ofstream f(path, std::ios::app);
+        f << key << " " << t.block_masses << " " << t.batch << " " << t.persistent << " " << t.us_per_step << " "
+          << t.us_default << "\n";
+    }
+}
+
 }  // namespace
 
 extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
@@ -236,13 +326,29 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     }
     if (d->group && ((int64_t)std::max(d->n_bodies, 1) * d->n_groups >= 65535 || d->n_groups < 1))
         return fail(CRONOS_EINVAL, "create: n_bodies * n_groups must be in [1, 65535)");
+    if (d->batch != 0 && d->batch != 2 && d->batch != 4 && d->batch != 8)
+        return fail(CRONOS_EINVAL, "create: batch must be 0, 2, 4 or 8");
+    if (d->persistent < -1 || d->persistent > 1) return fail(CRONOS_EINVAL, "create: persistent must be -1, 0 or 1");
+
+    // launch configuration: explicit values win, then a cached tuning result, then defaults
+    int32_t block = d->block_masses, batch = d->batch, persistent = d->persistent;
+    if (block == 0 || batch == 0 || persistent == 0) {
+        cronos_tune t{};
+        if (d->n_masses >= 1 && lookup_tune(tune_key(*d), &t)) {
+            if (block == 0) block = t.block_masses;
+            if (batch == 0) batch = t.batch;
+            if (persistent == 0) persistent = t.persistent;
+        }
+    }
+    if (batch == 0) batch = 4;
+    if (persistent < 0) persistent = 0;
 
     auto* sim = new (std::nothrow) cronos_sim_t;
     if (!sim) return fail(CRONOS_ENOMEM, "create: out of memory");
     cronos_status st;
     try {
-        st = cronos::build_layout(n, std::max(d->n_bodies, 1), d->body_offset, d->x0, d->grid, s, d->ends,
-                                  d->block_masses, sim->lay);
+        st = cronos::build_layout(n, std::max(d->n_bodies, 1), d->body_offset, d->x0, d->grid, s, d->ends, block,
+                                  sim->lay);
     } catch (const std::bad_alloc&) {
         st = fail(CRONOS_ENOMEM, "create: out of memory");
     }
@@ -351,8 +457,10 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     D.n = n;
     D.block = L.block;
     D.nblk = L.nblk;
+    D.nslice = L.nslice;
     D.lds_slots = L.block + L.max_halo;
     D.nb = sim->nb;
+    D.batch = batch;
     D.n_factor = n_factor;
     D.n_chunks = (int32_t)chunks.size();
     if (hipSetDevice(d->device) != hipSuccess) {
@@ -376,6 +484,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         TRY(upload<float>(&D.v[1], nullptr, 3 * n));
         TRY(upload(&D.mass, hm.data(), n));
         if (d->fext) TRY(upload(&D.fext, hf.data(), 3 * n));
+        TRY(upload(&D.lane_mass, L.lane_mass.data(), L.lane_mass.size()));
         TRY(upload(&D.slice_ptr, L.slice_ptr.data(), L.slice_ptr.size()));
         TRY(upload(&D.nbr, L.nbr_local.data(), entries));
         TRY(upload(&D.kl, hkl.data(), entries));
@@ -413,6 +522,17 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     P.ground_k = (float)d->ground_k;
     P.ground_mu = (float)d->ground_mu;
     P.exact = (d->flags & CRONOS_FAST_DIFF) ? 0 : 1;
+    if (persistent > 0) {
+        int g = 0;
+        hipError_t e = cronos::persistent_grid(D, P.exact, &g);
+        if (e != hipSuccess) {
+            free_device(sim);
+            delete sim;
+            return fail(CRONOS_EDEVICE, "create: occupancy query failed: %s", hipGetErrorString(e));
+        }
+        D.persistent_groups = g;
+    }
+    if (sim->actuated) sim->h_grp = std::move(hg);
     // the Morton-order host copies are only needed at creation
     sim->lay.nbr_local.clear();
     sim->lay.nbr_local.shrink_to_fit();
@@ -443,6 +563,8 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
     HIP_TRY(hipMemcpy(sim->d.phase, phase, m * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(sim->d.amp, amp, m * sizeof(double), hipMemcpyHostToDevice));
     sim->omega = 2.0 * M_PI * freq_hz;
+    sim->h_phase.assign(phase, phase + m);
+    sim->h_amp.assign(amp, amp + m);
     return CRONOS_OK;
 }
 
@@ -581,6 +703,231 @@ extern "C" cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t*
     if (n_bodies) *n_bodies = sim->nb;
     if (block_masses) *block_masses = sim->lay.block;
     if (step) *step = sim->step;
+    return CRONOS_OK;
+}
+
+namespace {
+
+template <typename T>
+cronos_status ensure(T** p, size_t count) {
+    if (*p) return CRONOS_OK;
+    if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+        return fail(CRONOS_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+    return CRONOS_OK;
+}
+
+template <typename T>
+void release(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t ckpt_every, const double* loss_w,
+                                        double* loss) {
+    cronos::clear_error();
+    if (!sim || !loss_w || !loss) return fail(CRONOS_EINVAL, "rollout: NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(CRONOS_EINVAL, "rollout: need n_steps >= 0 and ckpt_every >= 1");
+    const int64_t n = sim->d.n;
+    RolloutBuffers& R = sim->ro;
+    HIP_TRY(hipSetDevice(sim->device));
+    const int32_t K = (int32_t)std::min<int64_t>(ckpt_every, std::max<int64_t>(n_steps, 1));
+    const int32_t nseg = (int32_t)((n_steps + K - 1) / K);
+    if (R.cap_seg < (size_t)K || R.cap_ck < (size_t)nseg) {
+        HIP_TRY(hipStreamSynchronize(sim->stream));
+        release(R.ck_x); release(R.ck_v); release(R.seg_x); release(R.seg_v); release(R.seg_vs);
+        R.cap_seg = std::max<size_t>(R.cap_seg, (size_t)K);
+        R.cap_ck = std::max<size_t>(R.cap_ck, (size_t)std::max(nseg, 1));
+    }
+    TRY(ensure(&R.ck_x, R.cap_ck * n));
+    TRY(ensure(&R.ck_v, R.cap_ck * 3 * n));
+    TRY(ensure(&R.seg_x, (R.cap_seg + 1) * n));
+    TRY(ensure(&R.seg_v, (R.cap_seg + 1) * 3 * n));
+    TRY(ensure(&R.seg_vs, R.cap_seg * 3 * n));
+    TRY(ensure(&R.lossw, 3 * n));
+    TRY(ensure(&R.w, n));
+    for (int q = 0; q < 2; ++q) {
+        TRY(ensure(&R.xb[q], 3 * n));
+        TRY(ensure(&R.vb[q], 3 * n));
+    }
+    TRY(ensure(&R.xbl, 3 * n));
+    TRY(ensure(&R.sens, (size_t)sim->lay.slice_ptr.back()));
+    // loss weights in the device order (FP32)
+    std::vector<float> hw(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) hw[3 * i + c] = (float)loss_w[3 * sim->lay.perm[i] + c];
+    HIP_TRY(hipStreamSynchronize(sim->stream));
+    HIP_TRY(hipMemcpy(R.lossw, hw.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice));
+    R.n0 = sim->step;
+    R.T = n_steps;
+    R.K = K;
+    R.nseg = nseg;
+    for (int32_t c = 0; c < nseg; ++c) {
+        HIP_TRY(hipMemcpyAsync(R.ck_x + (size_t)c * n, sim->d.x[sim->cur], n * sizeof(float4), hipMemcpyDeviceToDevice,
+                               sim->stream));
+        HIP_TRY(hipMemcpyAsync(R.ck_v + (size_t)c * 3 * n, sim->d.v[sim->cur], 3 * n * sizeof(float),
+                               hipMemcpyDeviceToDevice, sim->stream));
+        TRY(cronos_step(sim, std::min<int64_t>(K, n_steps - (int64_t)c * K)));
+    }
+    std::vector<double> xT(3 * n);
+    TRY(cronos_read_state(sim, xT.data(), nullptr, nullptr));
+    double L = 0.0;
+    for (int64_t i = 0; i < 3 * n; ++i) L += loss_w[i] * xT[i];
+    *loss = L;
+    R.valid = true;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase, double* damp, double* dx0,
+                                                 double* dv0) {
+    cronos::clear_error();
+    if (!sim) return fail(CRONOS_EINVAL, "rollout_backward: NULL handle");
+    RolloutBuffers& R = sim->ro;
+    if (!R.valid) return fail(CRONOS_EINVAL, "rollout_backward: no rollout recorded");
+    const int64_t n = sim->d.n;
+    const int64_t entries = sim->lay.slice_ptr.back();
+    const cronos::DeviceArrays& D = sim->d;
+    hipStream_t st = sim->stream;
+    HIP_TRY(hipSetDevice(sim->device));
+    HIP_TRY(hipMemcpyAsync(R.xb[0], R.lossw, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(R.vb[0], 0, 3 * n * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
+    int cur = 0;
+    for (int32_t c = R.nseg - 1; c >= 0; --c) {
+        const int64_t nc = R.n0 + (int64_t)c * R.K;
+        const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
+        HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+        for (int32_t k = 0; k < steps; ++k) {
+            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->omega, sim->dt, 0, st, nc + k));
+            HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
+                                           R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
+                                           R.seg_vs + (size_t)k * 3 * n, sim->p, st));
+        }
+        for (int32_t k = steps - 1; k >= 0; --k) {
+            const double t = (double)(nc + k) * sim->dt;
+            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->omega, sim->dt, 0, st, nc + k));
+            HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)k * n, R.seg_vs + (size_t)k * 3 * n, R.xb[cur],
+                                             R.vb[cur], R.w, R.vb[cur ^ 1], R.xbl, sim->p, st));
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w, R.xbl, R.xb[cur ^ 1], R.sens,
+                                              std::cos(sim->omega * t), std::sin(sim->omega * t), st));
+            cur ^= 1;
+        }
+    }
+    // per-group reduction of the actuation sensitivities, FP64, in entry order
+    const int32_t G = sim->d.n_factor;
+    if ((dphase || damp) && G > 0 && sim->actuated) {
+        std::vector<double2> hs(entries);
+        HIP_TRY(hipMemcpyAsync(hs.data(), R.sens, entries * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<double> sp(G, 0.0), sq(G, 0.0);
+        for (int64_t e = 0; e < entries; ++e) {
+            const uint16_t g = sim->h_grp[e];
+            if (g < G) {
+                sp[g] += hs[e].x;
+                sq[g] += hs[e].y;
+            }
+        }
+        for (int32_t g = 0; g < G; ++g) {
+            const double ph = sim->h_phase.empty() ? 0.0 : sim->h_phase[g];
+            const double am = sim->h_amp.empty() ? 0.0 : sim->h_amp[g];
+            if (dphase) dphase[g] = am * (sp[g] * std::cos(ph) - sq[g] * std::sin(ph));
+            if (damp) damp[g] = sq[g] * std::cos(ph) + sp[g] * std::sin(ph);
+        }
+    } else {
+        for (int32_t g = 0; g < G; ++g) {
+            if (dphase) dphase[g] = 0.0;
+            if (damp) damp[g] = 0.0;
+        }
+    }
+    if (dx0 || dv0) {
+        std::vector<float> hx(3 * n), hv(3 * n);
+        HIP_TRY(hipMemcpyAsync(hx.data(), R.xb[cur], 3 * n * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hv.data(), R.vb[cur], 3 * n * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) {
+                if (dx0) dx0[3 * sim->lay.perm[i] + c] = hx[3 * i + c];
+                if (dv0) dv0[3 * sim->lay.perm[i] + c] = hv[3 * i + c];
+            }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch,
+                                              int32_t* persistent_groups) {
+    if (!sim) return fail(CRONOS_EINVAL, "launch_config: NULL handle");
+    if (block_masses) *block_masses = sim->lay.block;
+    if (batch) *batch = sim->d.batch;
+    if (persistent_groups) *persistent_groups = sim->d.persistent_groups;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, cronos_tune* out) {
+    cronos::clear_error();
+    if (!d || !out || n_steps < 1) return fail(CRONOS_EINVAL, "autotune: bad arguments");
+    cronos_tune best{};
+    best.us_per_step = 1e300;
+    best.us_default = 0.0;
+    const int blocks[] = {128, 256, 512, 1024};
+    const int batches[] = {2, 4, 8};
+    for (int blk : blocks) {
+        cronos_desc dd = *d;
+        dd.block_masses = blk;
+        dd.batch = 4;
+        dd.persistent = -1;
+        dd.flags |= CRONOS_ALLOW_UNSTABLE;   // checked once by the caller's own create
+        cronos_sim sim = nullptr;
+        cronos_status st = cronos_create(&dd, &sim);
+        if (st == CRONOS_EINVAL && blk != 256) continue;   // e.g. a halo too large for this size
+        if (st != CRONOS_OK) return st;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            cronos_destroy(sim);
+            return fail(CRONOS_EDEVICE, "autotune: hipEventCreate failed");
+        }
+        int pgrid = 0;
+        if (cronos::persistent_grid(sim->d, sim->p.exact, &pgrid) != hipSuccess) pgrid = 0;
+        for (int bt : batches) {
+            for (int pers = 0; pers < 2; ++pers) {
+                if (pers && pgrid <= 0) continue;
+                sim->d.batch = bt;
+                sim->d.persistent_groups = pers ? pgrid : 0;
+                sim->use_graph = false;
+                // warm up and time on the simulation's stream; the state evolves, which is
+                // harmless for timing (the tuner's simulation is discarded)
+                cronos_status s2 = enqueue_plain(sim, 3);
+                if (s2 == CRONOS_OK && hipEventRecord(e0, sim->stream) != hipSuccess) s2 = CRONOS_EDEVICE;
+                if (s2 == CRONOS_OK) s2 = enqueue_plain(sim, n_steps);
+                if (s2 == CRONOS_OK && hipEventRecord(e1, sim->stream) != hipSuccess) s2 = CRONOS_EDEVICE;
+                float ms = 0.0f;
+                if (s2 == CRONOS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    s2 = CRONOS_EDEVICE;
+                if (s2 != CRONOS_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    cronos_destroy(sim);
+                    return s2 == CRONOS_EDEVICE ? fail(CRONOS_EDEVICE, "autotune: timing failed") : s2;
+                }
+                const double us = 1e3 * (double)ms / n_steps;
+                if (blk == 256 && bt == 4 && !pers) best.us_default = us;
+                if (us < best.us_per_step) {
+                    best.us_per_step = us;
+                    best.block_masses = blk;
+                    best.batch = bt;
+                    best.persistent = pers;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        cronos_destroy(sim);
+    }
+    if (best.block_masses == 0) return fail(CRONOS_EDEVICE, "autotune: no configuration could be timed");
+    store_tune(tune_key(*d), best);
+    *out = best;
     return CRONOS_OK;
 }
 

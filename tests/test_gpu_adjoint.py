@@ -1,0 +1,130 @@
+"""GPU adjoint (cronos_rollout / cronos_rollout_backward) against the FP64 oracle adjoint and
+central finite differences of the FP64 oracle forward.  Bar: normwise relative error
+<= 1e-3 on the gradient with respect to the actuation phases and amplitudes."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as A
+from oracle import lattice as L
+from oracle import physics as P
+from paper_2207_09334_amd import cronos as CR
+from paper_2207_09334_amd import problem as PR
+from tests.gpu_common import oracle_problem, say
+
+pytestmark = pytest.mark.gpu
+
+G_TOL = 1e-3
+
+
+def _actuated_cube(ground: bool, groups=3, n=5, seed=11):
+    vox = W.box_voxels(n - 1, n - 1, n - 1)
+    rng = np.random.default_rng(seed)
+    mat = rng.integers(0, 3, len(vox)).astype(np.int32)
+    grp = (np.arange(len(vox)) % groups).astype(np.int32)
+    return W.Workload(
+        name="adj", bodies=[W.Body(vox, mat, grp)], spacing=0.01, origin=(0.0, 0.0, 0.0 if ground else 0.05),
+        mass_mode="uniform", mass_value=0.1, density=0.0, k_mode="assembly", k_uniform=0.0,
+        material_k=(1e3, 3e3, 1e4), jitter=0.0, pin_axis=-1, pin_index=0, gravity=(0.0, 0.0, -9.81),
+        damping=1e-3, dt=1e-4, ground=ground, ground_z=0.0, ground_k=1e5, ground_mu=0.8, steps=0,
+        n_groups=groups, freq_hz=20.0, phase=rng.uniform(0, 2 * np.pi, groups), amp=np.full(groups, 0.15))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def _compare(w, T, K, loss_w, fd_h=None):
+    lat, sys_, x0 = oracle_problem(w)
+    sim, _, _ = PR.create(w, x0=x0)
+    loss_g = CR.cronos_rollout(sim, T, K, loss_w)
+    dp, da, dx, dv = CR.cronos_rollout_backward(sim, want_state=True)
+    loss_o, op, oa, ox, ov = A.rollout_grad(sys_, x0, np.zeros_like(x0), 0, T, loss_w)
+    g_dev, g_ora = np.concatenate([dp, da]), np.concatenate([op, oa])
+    e = _rel(g_dev, g_ora)
+    say(f"  loss dev {loss_g:.9e} oracle {loss_o:.9e}; gradient rel err vs oracle adjoint {e:.2e}")
+    assert loss_g == pytest.approx(loss_o, rel=1e-5, abs=1e-9)
+    assert e <= G_TOL
+    if fd_h:
+        G = len(op)
+        fd = []
+        for which in ("phase", "amp"):
+            for g in range(G):
+                def s_(delta):
+                    ph, am = sys_.phase.copy(), sys_.amp.copy()
+                    (ph if which == "phase" else am)[g] += delta
+                    return dataclasses.replace(sys_, phase=ph, amp=am)
+                fd.append((A.rollout_loss(s_(fd_h), x0, np.zeros_like(x0), 0, T, loss_w) -
+                           A.rollout_loss(s_(-fd_h), x0, np.zeros_like(x0), 0, T, loss_w)) / (2 * fd_h))
+        e_fd = _rel(g_dev, fd)
+        say(f"  gradient rel err vs central differences {e_fd:.2e}")
+        assert e_fd <= G_TOL
+    return sim, dx, ox
+
+
+def test_adjoint_smooth_vs_oracle_and_fd():
+    w = _actuated_cube(ground=False)
+    say("case: adjoint, free actuated cube, 150 steps, checkpoints every 40")
+    lat = L.build(w)
+    loss_w = np.random.default_rng(3).normal(size=lat.x.shape) / lat.n_masses
+    sim, dx, ox = _compare(w, 150, 40, loss_w, fd_h=1e-6)
+    assert _rel(dx, ox) <= G_TOL
+
+
+def test_adjoint_contact_friction_vs_oracle_and_fd():
+    w = _actuated_cube(ground=True)
+    say("case: adjoint, actuated cube on the plane, 200 steps, checkpoints every 100")
+    lat = L.build(w)
+    loss_w = np.zeros_like(lat.x)
+    loss_w[:, 0] = lat.mass / lat.mass.sum()
+    _compare(w, 200, 100, loss_w, fd_h=1e-7)
+
+
+def test_adjoint_quadruped_vs_oracle():
+    """The quadruped (16 groups, 12,711 masses), forward-displacement loss, 300 steps in 3
+    checkpointed segments."""
+    w = W.quadruped()
+    say("case: adjoint, quadruped 300 steps, checkpoints every 100")
+    lat = L.build(w)
+    loss_w = np.zeros_like(lat.x)
+    loss_w[:, 0] = lat.mass / lat.mass.sum()
+    _compare(w, 300, 100, loss_w)
+
+
+def test_adjoint_quadruped_full_rollout_runs():
+    """The full 2000-step quadruped gradient with 20 checkpoints: finite, non-zero, and
+    repeatable bit for bit."""
+    w = W.quadruped()
+    say("case: adjoint, quadruped 2000 steps, checkpoints every 100")
+    sim, lat, x0 = PR.create(w)
+    lw = np.zeros_like(lat.x)
+    lw[:, 0] = lat.mass / lat.mass.sum()
+    out = []
+    for _ in range(2):
+        CR.cronos_set_state(sim, x0, np.zeros_like(x0), 0)
+        loss = CR.cronos_rollout(sim, 2000, 100, lw)
+        dp, da = CR.cronos_rollout_backward(sim)
+        out.append((loss, dp, da))
+    assert np.isfinite(out[0][1]).all() and np.isfinite(out[0][2]).all()
+    assert np.abs(out[0][1]).max() > 0 and np.abs(out[0][2]).max() > 0
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_autograd_function_drives_torch():
+    torch = pytest.importorskip("torch")
+    from paper_2207_09334_amd.autograd import RolloutGrad, forward_displacement_weights
+    w = _actuated_cube(ground=True)
+    sim, lat, x0 = PR.create(w)
+    lw = forward_displacement_weights(lat.mass)
+    phase = torch.tensor(w.phase, dtype=torch.float64, requires_grad=True)
+    amp = torch.tensor(w.amp, dtype=torch.float64, requires_grad=True)
+    loss = RolloutGrad.apply(phase, amp, sim, x0, np.zeros_like(x0), 0, 200, 50, lw, w.freq_hz)
+    loss.backward()
+    CR.cronos_set_state(sim, x0, np.zeros_like(x0), 0)
+    CR.cronos_set_actuation(sim, w.phase, w.amp, w.freq_hz)
+    CR.cronos_rollout(sim, 200, 50, lw)
+    dp, da = CR.cronos_rollout_backward(sim)
+    assert np.array_equal(phase.grad.numpy(), dp) and np.array_equal(amp.grad.numpy(), da)

@@ -174,14 +174,41 @@ def test_positions_population_small():
         assert a["ke"] == pytest.approx(o.ke, rel=1e-6, abs=1e-15)
 
 
+def test_population_full_size_sampled():
+    """The full 1024-robot population (about 11M masses) stepped together on the device,
+    300 steps in the benchmark's launch configuration; three sampled robots are re-simulated
+    alone by the oracle and compared (the robots are independent bodies).  Actuated contact
+    dynamics are sensitive, so the bar is max(1e-4, 30 x the FP32-rounding floor)."""
+    w = W.population(1024)
+    say("case: population 1024 robots, 300 steps, robots 0/511/1023 re-simulated by the oracle")
+    sim, lat, x0 = PR.create(w)
+    info = CR.cronos_info(sim)
+    say(f"  {info['n_masses']} masses, {info['n_springs']} springs")
+    CR.cronos_step(sim, 300)
+    xg, _, _ = CR.cronos_read_state(sim)
+    assert np.isfinite(xg).all()
+    for r in (0, 511, 1023):
+        wr = W.population(1, first_robot=r)
+        olat, osys, ox0 = oracle_problem(wr)
+        s, e = lat.body_offset[r], lat.body_offset[r + 1]
+        assert e - s == olat.n_masses
+        assert np.array_equal(x0[s:e], ox0)
+        xa, va = P.run(osys, ox0.copy(), np.zeros_like(ox0), 0, 300)
+        xb, vb = P.run(osys, ox0.astype(np.float32).astype(np.float64), np.zeros_like(ox0), 0, 300)
+        err, floor = position_error(xg[s:e], xa), position_error(xb, xa)
+        say(f"  robot {r}: {e - s} masses, err {err:.3e}, floor {floor:.3e}")
+        assert err <= max(X_TOL, 30.0 * floor)
+
+
 # ------------------------------------------------------------------------- determinism, invariants
 
 def test_bitwise_repeatable_and_block_size_independent():
     w = W.quadruped()
     say("case: determinism, quadruped 300 steps, blocks 256/512/1024 and graph/plain")
     outs = []
-    for blk, flags in ((256, 0), (256, 0), (512, 0), (1024, 0), (256, CR.NO_GRAPH), (64, 0)):
-        sim, _, _ = PR.create(w, block_masses=blk, flags=flags)
+    for blk, flags, batch, pers in ((256, 0, 4, -1), (256, 0, 4, -1), (512, 0, 2, -1), (1024, 0, 8, -1),
+                                    (256, CR.NO_GRAPH, 4, -1), (64, 0, 4, -1), (256, 0, 4, 1), (128, 0, 8, 1)):
+        sim, _, _ = PR.create(w, block_masses=blk, flags=flags, batch=batch, persistent=pers)
         CR.cronos_step(sim, 300)
         xg, vg, _ = CR.cronos_read_state(sim)
         outs.append((xg, vg))

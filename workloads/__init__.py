@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -284,9 +285,26 @@ def population_robot(seed: int, robot: int, lo: int = 500, hi: int = 50_000) -> 
     return Body(vox, mat, grp)
 
 
+def _robots(args):
+    seed, first, count, lo, hi = args
+    return [population_robot(seed, first + r, lo, hi) for r in range(count)]
+
+
 def population(n_robots: int = 1024, seed: int = 3, lo: int = 500, hi: int = 50_000,
-               first_robot: int = 0) -> Workload:
-    bodies = [population_robot(seed, first_robot + r, lo, hi) for r in range(n_robots)]
+               first_robot: int = 0, workers: Optional[int] = None) -> Workload:
+    """Population of independent random-walk robots.  Robots are generated in parallel
+    processes (spawned, so no state of the caller is inherited) when there are many."""
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if n_robots >= 64 else 1
+    if workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        per = (n_robots + workers - 1) // workers
+        jobs = [(seed, first_robot + k, min(per, n_robots - k), lo, hi) for k in range(0, n_robots, per)]
+        with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+            bodies = [b for part in ex.map(_robots, jobs) for b in part]
+    else:
+        bodies = _robots((seed, first_robot, n_robots, lo, hi))
     G = POP_GROUPS
     ph = np.concatenate([group_phases(seed, G, body=first_robot + r) for r in range(n_robots)])
     am = np.concatenate([group_amplitudes(seed, G, 0.0, 0.25, body=first_robot + r)
