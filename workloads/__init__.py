@@ -315,3 +315,35 @@ def population(n_robots: int = 1024, seed: int = 3, lo: int = 500, hi: int = 50_
         material_k=MATERIAL_K, jitter=0.0, pin_axis=-1, pin_index=0,
         gravity=(0.0, 0.0, -9.81), damping=1.0e-4, dt=1.0e-4, ground=True, ground_z=0.0,
         ground_k=1.0e5, ground_mu=0.8, steps=5000, n_groups=G, freq_hz=2.0, phase=ph, amp=am)
+
+
+# ----------------------------------------------------------------------------------------
+# surrogate network inputs
+# ----------------------------------------------------------------------------------------
+
+S_MLP = 8
+MLP_SIZES = (96, 256, 256, 256, 3)
+
+
+def mlp_init(seed: int = 4, sizes=MLP_SIZES) -> list:
+    """Initial weights [W1, b1, ..., W4, b4]: W_l uniform in +-sqrt(6 / (fan_in + fan_out))
+    (Glorot & Bengio 2010), keyed by (layer, row, column); biases zero."""
+    params = []
+    for l in range(len(sizes) - 1):
+        fi, fo = sizes[l], sizes[l + 1]
+        lim = math.sqrt(6.0 / (fi + fo))
+        r = np.arange(fi)[:, None]
+        c = np.arange(fo)[None, :]
+        params.append(lim * (2.0 * uniform01(seed, S_MLP, l, r, c) - 1.0))
+        params.append(np.zeros(fo))
+    return params
+
+
+def population_actuation(seed: int, n_robots: int, n_groups: int = 32, draw: int = 0, first_robot: int = 0):
+    """Phases in [0, 2 pi) and amplitudes in [0, 0.25] for every (robot, group); `draw` selects
+    an independent set for the same robots (training rollouts re-use morphologies)."""
+    r = np.arange(first_robot, first_robot + n_robots)[:, None]
+    g = np.arange(n_groups)[None, :]
+    ph = 2.0 * math.pi * uniform01(seed, S_PHASE, draw, r, g)
+    am = 0.25 * uniform01(seed, S_AMP, draw, r, g)
+    return ph.ravel(), am.ravel()
