@@ -83,6 +83,63 @@ def cpu_baseline(workload, steps: int):
                       f"({lat.n_masses} masses, {lat.n_springs} springs), single thread, {dt:.1f} s"}
 
 
+def surrogate_bench(args) -> dict:
+    """Surrogate screening vs the plain batched simulator.  A pool of robots (seed 4) is
+    simulated under `draws` actuation draws (5000 steps each); the first 7/8 of the robots
+    train the network, the last 1/8 are held-out candidates judged by the simulator."""
+    import numpy as np
+
+    from paper_2207_09334_amd import surrogate as SG
+
+    pool = SG.Pool(args.pool, seed=4, steps=5000)
+    n_train_robots = args.pool * 7 // 8
+    Xtr, Dtr, Xte, Dte, acts = [], [], [], [], []
+    for d in range(args.draws):
+        X, D = pool.draw(d)
+        Xtr.append(X[:n_train_robots])
+        Dtr.append(D[:n_train_robots])
+        Xte.append(X[n_train_robots:])
+        Dte.append(D[n_train_robots:])
+        acts.append(pool.actuation(d))
+    sim_rate = pool.rollouts_done / pool.sim_seconds
+    Xtr, Dtr, Dte = np.concatenate(Xtr), np.concatenate(Dtr), np.concatenate(Dte)
+    sur = SG.Surrogate(Xtr, Dtr, epochs=args.epochs, batch=1024)
+    # screening throughput: candidates arrive as (morphology, actuation); featurise + predict
+    from paper_2207_09334_amd import cronos as CR
+    held = pool.workload.bodies[n_train_robots:]
+    G = 32
+    t0 = time.perf_counter()
+    feats = [CR.cronos_features(held, pool.workload.material_k, pool.workload.spacing, G,
+                                ph.reshape(args.pool, G)[n_train_robots:].ravel(),
+                                am.reshape(args.pool, G)[n_train_robots:].ravel()) for ph, am in acts]
+    Xc = np.concatenate(feats)
+    pred = sur.predict(Xc)
+    flagged = sur.out_of_distribution(Xc)
+    t_screen = time.perf_counter() - t0
+    n_cand = len(Xc)
+    sur_rate = n_cand / t_screen
+    err = SG.rms_relative_error(pred, Dte)
+    per = np.linalg.norm(pred - Dte, axis=1) / np.sqrt((Dte ** 2).sum(axis=1).mean())
+    k = max(1, n_cand // 20)
+    chosen = SG.screen(pred, flagged, k)
+    true_top = set(np.argsort(-Dte[:, 0], kind="stable")[:k].tolist())
+    pred_top = set(np.argsort(-pred[:, 0], kind="stable")[:k].tolist())
+    # baseline without the network: a constant (training-mean) prediction
+    err_mean = SG.rms_relative_error(np.broadcast_to(Dtr.mean(axis=0), Dte.shape), Dte)
+    return {
+        "metric": "surrogate vs plain sim evals/sec", "value": sur_rate / sim_rate, "unit": "x",
+        "higher_is_better": True, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
+        "config": {"workload": f"surrogate_pool{args.pool}_draws{args.draws}", "rollout_steps": 5000,
+                   "train_rollouts": int(len(Xtr)), "heldout_candidates": int(n_cand), "epochs": args.epochs},
+        "surrogate_evals_per_s": sur_rate, "sim_evals_per_s": sim_rate,
+        "rms_rel_error": err, "p95_rel_error": float(np.percentile(per, 95)),
+        "rms_rel_error_constant_predictor": err_mean, "train_loss": sur.train_loss,
+        "train_seconds": sur.train_seconds, "flagged": int(flagged.sum()), "simulated_after_screen": int(len(chosen)),
+        "top5pct_overlap": len(true_top & pred_top) / k,
+        "best_true_x_in_screened": float(Dte[chosen, 0].max()), "best_true_x_overall": float(Dte[:, 0].max()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +151,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
-    ap.add_argument("--workload", choices=("cantilever", "population"), default="cantilever")
+    ap.add_argument("--workload", choices=("cantilever", "population", "surrogate"), default="cantilever")
+    ap.add_argument("--pool", type=int, default=2048, help="surrogate: robots in the morphology pool")
+    ap.add_argument("--draws", type=int, default=40, help="surrogate: actuation draws simulated per robot")
+    ap.add_argument("--epochs", type=int, default=60, help="surrogate: training epochs")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -108,6 +168,10 @@ def main():
 
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import torch
+
+    if args.workload == "surrogate":
+        print(json.dumps(surrogate_bench(args)), flush=True)
+        return
 
     import workloads as W
     from paper_2207_09334_amd import cronos as CR

@@ -45,6 +45,8 @@ typedef enum {
 #define CRONOS_ALLOW_UNSTABLE 0x1u   /* skip the stability check at creation                 */
 #define CRONOS_CHECK_LAYOUT   0x2u   /* verify the device layout against the CSR at creation  */
 #define CRONOS_NO_GRAPH       0x4u   /* enqueue steps as plain launches, not HIP graphs      */
+#define CRONOS_NO_TABLE       0x10u  /* keep explicit per-entry (k, L0) in the step instead of a
+                                        16-bit index into the table of distinct pairs        */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -267,6 +269,51 @@ cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t ckpt_every
  * FP64 accumulation of the actuation sensitivities).  Blocking.  Does not change the state.
  * Errors: EINVAL (no rollout recorded), EDEVICE. */
 cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase, double* damp, double* dx0, double* dv0);
+
+/* ------------------------------------------------------------------------------------------
+ * Learned surrogate (not in the paper): predicts a robot's displacement from its morphology
+ * and actuation, to pre-screen candidates before the simulator judges them.
+ * ---------------------------------------------------------------------------------------- */
+
+/* Features of n_bodies voxel robots (host, parallel over robots): 32 morphology descriptors
+ * (log node count, log voxel count, extent per axis, fractions of materials 0/1/2, mean voxel
+ * centre minus bbox centre, second moments xx yy zz xy xz yz, bottom-layer fraction, 8-bin
+ * height histogram, actuated fraction, mean log10 voxel stiffness, stiffness-weighted centre
+ * offset, surface-face fraction) then (A_g cos phi_g, A_g sin phi_g) for g < n_groups.
+ * voxels [n_voxels][3]; body_voxel_offset [n_bodies+1] (required); material, group [n_voxels]
+ * or NULL; phase, amp [n_bodies*n_groups]; out [n_bodies][32 + 2 n_groups] (FP64).
+ * Errors: EINVAL, ENOMEM. */
+cronos_status cronos_features(int32_t n_bodies, const int64_t* body_voxel_offset, const int32_t* voxels,
+                              const int32_t* material, const int32_t* group, int32_t n_materials,
+                              const double* material_k, double spacing, int32_t n_groups, const double* phase,
+                              const double* amp, double* out);
+
+/* Perceptron sizes[0] -> sizes[1] -> sizes[2] -> sizes[3] -> sizes[4] with exact-erf GELU
+ * after the three hidden layers and a linear output.  Products on the BF16 matrix cores with
+ * FP32 accumulation; an FP32 master copy of the weights with a BF16 shadow; hidden activations
+ * and back-propagated gradients stored in BF16; MSE loss; Adam in FP32. */
+typedef struct cronos_mlp_t* cronos_mlp;
+
+/* params: FP64 host [W1 (sizes[0] x sizes[1], row-major), b1, W2, b2, W3, b3, W4, b4];
+ * max_rows: largest batch of a single forward/gradient call.  Errors: EINVAL, ENOMEM, EDEVICE. */
+cronos_status cronos_mlp_create(const int32_t* sizes, const double* params, int32_t max_rows, int32_t device,
+                                void* stream, cronos_mlp* out);
+void cronos_mlp_destroy(cronos_mlp mlp);
+/* Current FP32 master weights, widened, in the layout of cronos_mlp_create. */
+cronos_status cronos_mlp_get_params(cronos_mlp mlp, double* params);
+/* y [rows][sizes[4]] = network(x [rows][sizes[0]]) (host FP32 arrays; any number of rows). */
+cronos_status cronos_mlp_forward(cronos_mlp mlp, const float* x, int64_t rows, float* y);
+/* Mean squared error on (x, t) (rows <= max_rows) and its gradient (FP32 widened; the layout
+ * of the parameters; NULL skips); the gradient stays on the device for cronos_mlp_adam. */
+cronos_status cronos_mlp_loss_grad(cronos_mlp mlp, const float* x, const float* t, int32_t rows, double* loss,
+                                   double* grads);
+/* One Adam step (Kingma & Ba) with the last computed gradient. */
+cronos_status cronos_mlp_adam(cronos_mlp mlp, double lr, double beta1, double beta2, double eps);
+/* Train in place: `epochs` passes over (x, t) [rows] in minibatches of `batch` (<= max_rows),
+ * shuffled every epoch by a SplitMix64-driven Fisher-Yates permutation of `seed`; Adam with
+ * lr, 0.9, 0.999, 1e-8.  epoch_loss: mean minibatch loss of the last epoch. */
+cronos_status cronos_mlp_train(cronos_mlp mlp, const float* x, const float* t, int64_t rows, int32_t batch,
+                               int32_t epochs, double lr, uint64_t seed, double* epoch_loss);
 
 /* Input-order layout of a created simulation (see cronos_layout_get). */
 cronos_status cronos_get_layout(cronos_sim sim, int32_t* perm, int64_t* row_ptr, int32_t* col,

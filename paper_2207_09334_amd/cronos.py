@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcronos.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF = 0x1, 0x2, 0x4, 0x8
+ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE = 0x1, 0x2, 0x4, 0x8, 0x10
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -101,6 +101,14 @@ _SIGS = {
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
     "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
     "cronos_rollout_backward": (C.c_int, [_p, _p, _p, _p, _p]),
+    "cronos_features": (C.c_int, [_i32, _p, _p, _p, _p, _i32, _p, _f64, _i32, _p, _p, _p]),
+    "cronos_mlp_create": (C.c_int, [_p, _p, _i32, _i32, _p, C.POINTER(_p)]),
+    "cronos_mlp_destroy": (None, [_p]),
+    "cronos_mlp_get_params": (C.c_int, [_p, _p]),
+    "cronos_mlp_forward": (C.c_int, [_p, _p, _i64, _p]),
+    "cronos_mlp_loss_grad": (C.c_int, [_p, _p, _p, _i32, C.POINTER(_f64), _p]),
+    "cronos_mlp_adam": (C.c_int, [_p, _f64, _f64, _f64, _f64]),
+    "cronos_mlp_train": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, C.c_uint64, C.POINTER(_f64)]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -351,3 +359,104 @@ def cronos_rollout_backward(sim: Sim, want_state=False):
     dv = np.empty((sim.n_masses, 3)) if want_state else None
     _check(_lib.cronos_rollout_backward(sim.handle, _ptr(dp), _ptr(da), _ptr(dx), _ptr(dv)))
     return (dp, da, dx, dv) if want_state else (dp, da)
+
+
+# ------------------------------------------------------------------------------ surrogate
+
+def cronos_features(bodies, material_k, spacing, n_groups, phase, amp) -> np.ndarray:
+    """bodies: sequence of objects with .voxels, .material, .group (workloads.Body)."""
+    vox = _arr(np.concatenate([b.voxels for b in bodies]), np.int32, (-1, 3))
+    off = _arr(np.cumsum([0] + [len(b.voxels) for b in bodies]), np.int64)
+    mat = grp = None
+    if any(b.material is not None for b in bodies):
+        mat = _arr(np.concatenate([b.material if b.material is not None else np.zeros(len(b.voxels))
+                                   for b in bodies]), np.int32)
+    if any(b.group is not None for b in bodies):
+        grp = _arr(np.concatenate([b.group if b.group is not None else np.full(len(b.voxels), -1)
+                                   for b in bodies]), np.int32)
+    mk = _arr(material_k, np.float64)
+    ph, am = _arr(phase, np.float64), _arr(amp, np.float64)
+    out = np.empty((len(bodies), 32 + 2 * n_groups))
+    _check(_lib.cronos_features(len(bodies), _ptr(off), _ptr(vox), _ptr(mat), _ptr(grp),
+                                0 if mk is None else len(mk), _ptr(mk), spacing, n_groups, _ptr(ph), _ptr(am),
+                                _ptr(out)))
+    return out
+
+
+class MLP:
+    def __init__(self, handle, sizes):
+        self.handle, self.sizes = handle, tuple(sizes)
+
+    def close(self):
+        if self.handle:
+            _lib.cronos_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_params(self):
+        s = self.sizes
+        return sum(s[l] * s[l + 1] + s[l + 1] for l in range(4))
+
+
+def _flat(params) -> np.ndarray:
+    return np.concatenate([np.asarray(p, np.float64).ravel() for p in params])
+
+
+def _unflat(flat, sizes):
+    out, o = [], 0
+    for l in range(4):
+        fi, fo = sizes[l], sizes[l + 1]
+        out.append(flat[o:o + fi * fo].reshape(fi, fo))
+        o += fi * fo
+        out.append(flat[o:o + fo].copy())
+        o += fo
+    return out
+
+
+def cronos_mlp_create(params, sizes=(96, 256, 256, 256, 3), max_rows=4096, device=0, stream=None) -> MLP:
+    sz = _arr(sizes, np.int32)
+    fl = _flat(params)
+    h = _p()
+    _check(_lib.cronos_mlp_create(_ptr(sz), _ptr(fl), int(max_rows), device, stream, C.byref(h)))
+    return MLP(h, sizes)
+
+
+def cronos_mlp_get_params(mlp: MLP) -> list:
+    fl = np.empty(mlp.n_params)
+    _check(_lib.cronos_mlp_get_params(mlp.handle, _ptr(fl)))
+    return _unflat(fl, mlp.sizes)
+
+
+def cronos_mlp_forward(mlp: MLP, x) -> np.ndarray:
+    xx = _arr(x, np.float32, (-1, mlp.sizes[0]))
+    y = np.empty((len(xx), mlp.sizes[4]), np.float32)
+    _check(_lib.cronos_mlp_forward(mlp.handle, _ptr(xx), len(xx), _ptr(y)))
+    return y
+
+
+def cronos_mlp_loss_grad(mlp: MLP, x, t):
+    xx = _arr(x, np.float32, (-1, mlp.sizes[0]))
+    tt = _arr(t, np.float32, (-1, mlp.sizes[4]))
+    loss = _f64()
+    g = np.empty(mlp.n_params)
+    _check(_lib.cronos_mlp_loss_grad(mlp.handle, _ptr(xx), _ptr(tt), len(xx), C.byref(loss), _ptr(g)))
+    return loss.value, _unflat(g, mlp.sizes)
+
+
+def cronos_mlp_adam(mlp: MLP, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_lib.cronos_mlp_adam(mlp.handle, lr, beta1, beta2, eps))
+
+
+def cronos_mlp_train(mlp: MLP, x, t, batch=1024, epochs=1, lr=1e-3, seed=4) -> float:
+    xx = _arr(x, np.float32, (-1, mlp.sizes[0]))
+    tt = _arr(t, np.float32, (-1, mlp.sizes[4]))
+    out = _f64()
+    _check(_lib.cronos_mlp_train(mlp.handle, _ptr(xx), _ptr(tt), len(xx), int(batch), int(epochs), float(lr),
+                                 C.c_uint64(seed), C.byref(out)))
+    return out.value

@@ -32,6 +32,9 @@ struct DeviceArrays {
     int32_t* slice_ptr = nullptr;
     uint16_t* nbr = nullptr;
     float2* kl = nullptr;                // (k, L0) per entry
+    uint32_t* packed = nullptr;          // compact entries: LDS slot | table index << 16 (or null)
+    float2* table = nullptr;             // distinct (k, L0) pairs of the compact entries
+    int32_t n_table = 0;
     uint16_t* grp = nullptr;             // per entry index into factor[], or null
     int32_t* halo_ptr = nullptr;
     int32_t* halo_idx = nullptr;

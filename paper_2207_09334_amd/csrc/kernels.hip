@@ -152,6 +152,48 @@ __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi,
     }
 }
 
+// The same sum over the compact entry stream: one 32-bit word per entry holding the LDS slot
+// (low 16 bits) and the index of the spring's (k, L0) pair in the simulation's parameter
+// table (high 16 bits), the table being staged in LDS (st).
+template <bool ACT, bool EXACT, int BATCH>
+__device__ __forceinline__ void gather_table(const float4* __restrict__ sx, const float2* __restrict__ st, float4 xi,
+                                             int s, int nslice, const int32_t* __restrict__ slice_ptr,
+                                             const uint32_t* __restrict__ packed, const uint16_t* __restrict__ grp,
+                                             const float* __restrict__ factor, float& fx, float& fy, float& fz) {
+    fx = fy = fz = 0.0f;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s >= nslice) return;
+    const int lane = threadIdx.x & 63;
+    const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
+    const int w = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
+    const uint32_t* pp = packed + e0 + lane;
+    const uint16_t* pg = ACT ? grp + e0 + lane : nullptr;
+    int r = 0;
+    for (; r + BATCH <= w; r += BATCH) {
+        uint32_t q[BATCH];
+        float f[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            q[u] = pp[(r + u) * 64];
+            if (ACT) f[u] = factor[pg[(r + u) * 64]];
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const float4 xj = sx[q[u] & 0xFFFFu];
+            const float2 c = st[q[u] >> 16];
+            const float l0 = ACT ? c.y * f[u] : c.y;
+            hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
+        }
+    }
+    for (; r < w; ++r) {
+        const uint32_t q = pp[r * 64];
+        const float2 c = st[q >> 16];
+        const float l0 = ACT ? c.y * factor[pg[r * 64]] : c.y;
+        const float4 xj = sx[q & 0xFFFFu];
+        hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
+    }
+}
+
 struct StepArgs {
     const float4* __restrict__ xin;
     const float* __restrict__ vin;
@@ -167,19 +209,28 @@ struct StepArgs {
     const float* __restrict__ factor;
     const float* __restrict__ fext;
     float* __restrict__ vstar_out;   // optional: velocity before friction and damping (adjoint recompute)
-    int n, nblk, nslice, block;
+    const uint32_t* __restrict__ packed;   // compact entries (slot | table index << 16), or null
+    const float2* __restrict__ table;      // (k, L0) pairs of the compact entries
+    int n, nblk, nslice, block, n_table, lds_slots;
 };
 
 // One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
 // damping, symplectic Euler, fixed masses.
-template <bool ACT, bool EXACT, int BATCH>
+template <bool ACT, bool EXACT, int BATCH, bool TABLE>
 __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b) {
     const int base = b * a.block;
+    float2* st = reinterpret_cast<float2*>(sx + a.lds_slots);
+    if (TABLE)
+        for (int q = threadIdx.x; q < a.n_table; q += a.block) st[q] = a.table[q];
     const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
     const float4 xi = sx[own];
     float fx, fy, fz;
-    gather<ACT, EXACT, BATCH>(sx, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp,
-                              a.factor, fx, fy, fz);
+    if (TABLE)
+        gather_table<ACT, EXACT, BATCH>(sx, st, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.packed,
+                                        a.grp, a.factor, fx, fy, fz);
+    else
+        gather<ACT, EXACT, BATCH>(sx, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp,
+                                  a.factor, fx, fy, fz);
     const int i = base + own;
     if (i >= a.n) return;
 
@@ -234,17 +285,17 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
 }
 
 // One workgroup per block.
-template <bool ACT, bool EXACT, int BATCH>
+template <bool ACT, bool EXACT, int BATCH, bool TABLE>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     const int b = logical_block(a.nblk);
     if (b >= a.nblk) return;
-    step_block<ACT, EXACT, BATCH>(sx, a, p, b);
+    step_block<ACT, EXACT, BATCH, TABLE>(sx, a, p, b);
 }
 
 // Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
 // on XCD w % 8 and takes that XCD's contiguous eighth of the blocks in strides.
-template <bool ACT, bool EXACT, int BATCH>
+template <bool ACT, bool EXACT, int BATCH, bool TABLE>
 __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     const int per = (a.nblk + 7) >> 3;
@@ -253,7 +304,7 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
     for (int j = (int)(blockIdx.x >> 3); j < per; j += stride) {
         const int b = xcd * per + j;
         if (b >= a.nblk) break;
-        step_block<ACT, EXACT, BATCH>(sx, a, p, b);
+        step_block<ACT, EXACT, BATCH, TABLE>(sx, a, p, b);
         __syncthreads();  // LDS is restaged for the next block
     }
 }
@@ -584,31 +635,31 @@ hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipS
 
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
                           float* vstar, const StepParams& p, hipStream_t st) {
+    const bool table = d.packed != nullptr;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
-               d.lane_mass, d.factor, d.fext, vstar, (int)d.n, (int)d.nblk, (int)d.nslice, d.block};
-    const size_t lds = (size_t)d.lds_slots * sizeof(float4);
+               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.table, (int)d.n, (int)d.nblk, (int)d.nslice, d.block,
+               d.n_table, d.lds_slots};
+    const size_t lds = (size_t)d.lds_slots * sizeof(float4) + (table ? (size_t)d.n_table * sizeof(float2) : 0);
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
     auto go = [&](auto normal, auto pers) {
         if (persistent) hipLaunchKernelGGL(pers, grid, dim3(d.block), lds, st, a, p);
         else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds, st, a, p);
     };
-#define CRONOS_GO(A, E, B) go(step_kernel<A, E, B>, step_persistent<A, E, B>)
+#define CRONOS_GO(A, E, B, T) go(step_kernel<A, E, B, T>, step_persistent<A, E, B, T>)
+#define CRONOS_GO_T(A, E, B) (table ? CRONOS_GO(A, E, B, true) : CRONOS_GO(A, E, B, false))
     const bool act = d.grp != nullptr, ex = p.exact != 0;
-    switch (d.batch) {
-        case 2:
-            if (act) ex ? CRONOS_GO(true, true, 2) : CRONOS_GO(true, false, 2);
-            else ex ? CRONOS_GO(false, true, 2) : CRONOS_GO(false, false, 2);
-            break;
-        case 8:
-            if (act) ex ? CRONOS_GO(true, true, 8) : CRONOS_GO(true, false, 8);
-            else ex ? CRONOS_GO(false, true, 8) : CRONOS_GO(false, false, 8);
-            break;
-        default:
-            if (act) ex ? CRONOS_GO(true, true, 4) : CRONOS_GO(true, false, 4);
-            else ex ? CRONOS_GO(false, true, 4) : CRONOS_GO(false, false, 4);
-            break;
+    if (d.batch == 8) {
+        if (act) ex ? CRONOS_GO_T(true, true, 8) : CRONOS_GO_T(true, false, 8);
+        else ex ? CRONOS_GO_T(false, true, 8) : CRONOS_GO_T(false, false, 8);
+    } else if (d.batch == 2) {
+        if (act) ex ? CRONOS_GO_T(true, true, 2) : CRONOS_GO_T(true, false, 2);
+        else ex ? CRONOS_GO_T(false, true, 2) : CRONOS_GO_T(false, false, 2);
+    } else {
+        if (act) ex ? CRONOS_GO_T(true, true, 4) : CRONOS_GO_T(true, false, 4);
+        else ex ? CRONOS_GO_T(false, true, 4) : CRONOS_GO_T(false, false, 4);
     }
+#undef CRONOS_GO_T
 #undef CRONOS_GO
     return hipGetLastError();
 }
@@ -618,9 +669,10 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)d.lds_slots * sizeof(float4);
-    const void* k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4> : (const void*)step_persistent<true, false, 4>)
-                          : (exact ? (const void*)step_persistent<false, true, 4> : (const void*)step_persistent<false, false, 4>);
+    const bool table = d.packed != nullptr;
+    const size_t lds = (size_t)d.lds_slots * sizeof(float4) + (table ? (size_t)d.n_table * sizeof(float2) : 0);
+    const void* k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4, true> : (const void*)step_persistent<true, false, 4, true>)
+                          : (exact ? (const void*)step_persistent<false, true, 4, true> : (const void*)step_persistent<false, false, 4, true>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, lds);
     if (e != hipSuccess) return e;
     int g = std::max(1, per_cu) * cus;

@@ -12,6 +12,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 
 #include "common.h"
 #include "kernels.h"
@@ -99,7 +100,7 @@ namespace {
 
 void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
-    void* ptrs[] = {d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
+    void* ptrs[] = {d.packed, d.table, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
                     d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
                     d.body_out, d.fout};
     for (void* p : ptrs)
@@ -432,6 +433,41 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         if (sim->actuated && d->group[si] >= 0) hg[e] = (uint16_t)(spring_body[sn] * sim->n_groups + d->group[si]);
     }
 
+    // compact entry stream: the distinct (k, L0) pairs (in order of first use) and one 32-bit
+    // word per entry, slot | pair index << 16; skipped when there are too many pairs
+    constexpr int kMaxTable = 1024;
+    std::vector<float2> htable;
+    std::vector<uint32_t> hpacked;
+    if (!(d->flags & CRONOS_NO_TABLE)) {
+        std::unordered_map<uint64_t, uint32_t> index;
+        hpacked.resize(entries);
+        bool ok = true;
+        for (int64_t e = 0; e < entries && ok; ++e) {
+            uint32_t kb, lb;
+            std::memcpy(&kb, &hkl[e].x, 4);
+            std::memcpy(&lb, &hkl[e].y, 4);
+            const uint64_t key = ((uint64_t)kb << 32) | lb;
+            auto it = index.find(key);
+            uint32_t id;
+            if (it == index.end()) {
+                if ((int)htable.size() >= kMaxTable) {
+                    ok = false;
+                    break;
+                }
+                id = (uint32_t)htable.size();
+                index.emplace(key, id);
+                htable.push_back(hkl[e]);
+            } else {
+                id = it->second;
+            }
+            hpacked[e] = (uint32_t)L.nbr_local[e] | (id << 16);
+        }
+        if (!ok) {
+            htable.clear();
+            hpacked.clear();
+        }
+    }
+
     // diagnostics chunks: workgroup blocks split at body boundaries
     std::vector<int4> chunks;
     std::vector<int32_t> body_chunk(sim->nb + 1, 0);
@@ -467,7 +503,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         delete sim;
         return fail(CRONOS_EDEVICE, "create: hipSetDevice(%d) failed", d->device);
     }
-    if ((size_t)D.lds_slots * sizeof(float4) > 160 * 1024) {
+    if ((size_t)D.lds_slots * sizeof(float4) + 1024 * sizeof(float2) > 160 * 1024) {
         delete sim;
         return fail(CRONOS_EINVAL, "create: workgroup halo needs %zu bytes of LDS", (size_t)D.lds_slots * sizeof(float4));
     }
@@ -488,6 +524,11 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         TRY(upload(&D.slice_ptr, L.slice_ptr.data(), L.slice_ptr.size()));
         TRY(upload(&D.nbr, L.nbr_local.data(), entries));
         TRY(upload(&D.kl, hkl.data(), entries));
+        if (!htable.empty()) {
+            TRY(upload(&D.packed, hpacked.data(), entries));
+            TRY(upload(&D.table, htable.data(), htable.size()));
+            D.n_table = (int32_t)htable.size();
+        }
         if (sim->actuated) TRY(upload(&D.grp, hg.data(), entries));
         TRY(upload(&D.halo_ptr, L.halo_ptr.data(), L.halo_ptr.size()));
         TRY(upload(&D.halo_idx, L.halo_idx.data(), L.halo_idx.size()));

@@ -204,10 +204,12 @@ def test_population_full_size_sampled():
 
 def test_bitwise_repeatable_and_block_size_independent():
     w = W.quadruped()
-    say("case: determinism, quadruped 300 steps, blocks 256/512/1024 and graph/plain")
+    say("case: determinism, quadruped 300 steps: workgroup sizes, batches, launch forms, graph/plain, "
+        "table/explicit parameters")
     outs = []
     for blk, flags, batch, pers in ((256, 0, 4, -1), (256, 0, 4, -1), (512, 0, 2, -1), (1024, 0, 8, -1),
-                                    (256, CR.NO_GRAPH, 4, -1), (64, 0, 4, -1), (256, 0, 4, 1), (128, 0, 8, 1)):
+                                    (256, CR.NO_GRAPH, 4, -1), (64, 0, 4, -1), (256, 0, 4, 1), (128, 0, 8, 1),
+                                    (256, CR.NO_TABLE, 4, -1), (512, CR.NO_TABLE, 8, 1)):
         sim, _, _ = PR.create(w, block_masses=blk, flags=flags, batch=batch, persistent=pers)
         CR.cronos_step(sim, 300)
         xg, vg, _ = CR.cronos_read_state(sim)

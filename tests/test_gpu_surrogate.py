@@ -1,0 +1,116 @@
+"""GPU surrogate network (BF16 MFMA, FP32 accumulation) against the FP64 oracle network that
+rounds inputs, weights, hidden activations and back-propagated gradients to BF16 as the
+device stores them; the remaining differences are FP32 accumulation and FP32 erf/exp."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as M
+from paper_2207_09334_amd import cronos as CR
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(rows, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(rows, 96)), rng.normal(size=(rows, 3))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("rows", [1, 64, 200, 4096])
+def test_forward_matches_oracle(rows):
+    params = W.mlp_init(4)
+    params = [p + 0.05 * np.random.default_rng(1).normal(size=p.shape) for p in params]   # non-zero biases
+    X, _ = _data(rows)
+    net = CR.cronos_mlp_create(params, max_rows=4096)
+    y = CR.cronos_mlp_forward(net, X.astype(np.float32))
+    ref, _ = M.forward(params, X.astype(np.float32).astype(np.float64), storage="bf16")
+    e = _rel(y, ref)
+    say(f"  rows {rows}: forward rel err {e:.2e}; max abs {np.abs(y - ref).max():.2e}")
+    assert e <= 1e-2
+    # without the storage model the gap is the BF16 rounding itself (~1e-2): the device does
+    # not skip it
+    assert _rel(y, M.forward(params, X, storage="fp64")[0]) <= 5e-2
+
+
+def test_forward_beyond_max_rows_is_chunked():
+    params = W.mlp_init(4)
+    X, _ = _data(700)
+    net = CR.cronos_mlp_create(params, max_rows=256)
+    y = CR.cronos_mlp_forward(net, X.astype(np.float32))
+    net2 = CR.cronos_mlp_create(params, max_rows=1024)
+    assert np.array_equal(y, CR.cronos_mlp_forward(net2, X.astype(np.float32)))
+
+
+def test_gradients_match_oracle():
+    params = W.mlp_init(4)
+    params = [p + 0.05 * np.random.default_rng(2).normal(size=p.shape) for p in params]
+    X, T = _data(300, seed=3)
+    net = CR.cronos_mlp_create(params, max_rows=512)
+    loss, g = CR.cronos_mlp_loss_grad(net, X.astype(np.float32), T.astype(np.float32))
+    lo, go = M.loss_and_grad(params, X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64),
+                             storage="bf16")
+    say(f"  loss dev {loss:.6e} oracle {lo:.6e}")
+    assert loss == pytest.approx(lo, rel=1e-2)
+    for l in range(8):
+        e = _rel(g[l], go[l])
+        say(f"  grad {l}: rel err {e:.2e}")
+        assert e <= 2e-2
+
+
+def test_adam_step_matches_oracle():
+    params = W.mlp_init(4)
+    X, T = _data(256, seed=5)
+    net = CR.cronos_mlp_create(params, max_rows=256)
+    _, g = CR.cronos_mlp_loss_grad(net, X.astype(np.float32), T.astype(np.float32))
+    CR.cronos_mlp_adam(net, lr=1e-3)
+    after = CR.cronos_mlp_get_params(net)
+    ref = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    m = [np.zeros_like(p) for p in ref]
+    v = [np.zeros_like(p) for p in ref]
+    M.adam_step(ref, g, m, v, 1, lr=1e-3)
+    for a, r in zip(after, ref):
+        np.testing.assert_allclose(a, r, rtol=1e-5, atol=1e-7)
+
+
+def test_training_fits_a_smooth_function():
+    """Device training on y = smooth function of x reaches a small fraction of the initial
+    loss; the oracle network trained the same way (FP64) lands in the same range."""
+    rng = np.random.default_rng(7)
+    X = rng.normal(size=(8192, 96))
+    Wt = rng.normal(size=(96, 3)) / 10
+    T = np.tanh(X @ Wt) + 0.1 * (X[:, :3] ** 2)
+    net = CR.cronos_mlp_create(W.mlp_init(4), max_rows=1024)
+    l0 = CR.cronos_mlp_loss_grad(net, X[:1024].astype(np.float32), T[:1024].astype(np.float32))[0]
+    last = CR.cronos_mlp_train(net, X.astype(np.float32), T.astype(np.float32), batch=512, epochs=30, lr=1e-3, seed=1)
+    say(f"  initial loss {l0:.4f}, last-epoch loss {last:.4f}")
+    assert last < 0.05 * l0
+
+
+def test_screening_pipeline_small():
+    """A 48-robot pool, 8 actuation draws of 400 steps: the judge (simulator) is bitwise
+    repeatable, training runs on the device, predictions are finite, out-of-distribution
+    candidates are flagged and always handed to the simulator."""
+    from paper_2207_09334_amd import surrogate as SG
+    pool = SG.Pool(48, seed=4, steps=400, lo=300, hi=3000)
+    Xs, Ds = zip(*[pool.draw(d) for d in range(8)])
+    X0, D0 = pool.draw(0)
+    assert np.array_equal(D0, Ds[0]) and np.array_equal(X0, Xs[0])
+    X, D = np.concatenate(Xs), np.concatenate(Ds)
+    robot = np.tile(np.arange(48), 8)
+    train, held = robot < 40, robot >= 40
+    sur = SG.Surrogate(X[train], D[train], epochs=40, batch=128, max_rows=512)
+    pred = sur.predict(X[held])
+    assert np.isfinite(pred).all() and pred.shape == (held.sum(), 3)
+    say(f"  small pool: train loss {sur.train_loss:.3f}, held-out rms rel err "
+        f"{SG.rms_relative_error(pred, D[held]):.3f}")
+    far = X[held][:3].copy()
+    far[0, 0] += 100.0                                   # an absurd node count
+    flags = sur.out_of_distribution(far)
+    assert flags[0] and not flags[1:].any()
+    chosen = SG.screen(sur.predict(far), flags, top_k=1)
+    assert 0 in chosen

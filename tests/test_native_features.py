@@ -1,0 +1,60 @@
+"""Surrogate features: native featurizer vs hand-computed values and vs the oracle (CPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import features as F
+
+CR = pytest.importorskip("paper_2207_09334_amd.cronos")
+
+A = 0.01
+K = (1.0e3, 1.0e4, 1.0e5)
+
+
+def _native(bodies, phase, amp, groups=2):
+    return CR.cronos_features(bodies, K, A, groups, phase, amp)
+
+
+def test_single_voxel_by_hand():
+    b = W.Body(np.array([[3, -2, 5]]), np.array([1], np.int32), np.array([0], np.int32))
+    f = _native([b], [0.3, 1.1], [0.2, 0.1])[0]
+    expect = np.zeros(36)
+    expect[0] = math.log(8)
+    expect[2:5] = A
+    expect[6] = 1.0                       # material 1
+    expect[17] = 1.0                      # bottom layer
+    expect[18] = 1.0                      # lowest height bin
+    expect[26] = 1.0                      # actuated
+    expect[27] = 4.0                      # log10(1e4)
+    expect[31] = 1.0                      # all six faces exposed
+    expect[32:36] = [0.2 * math.cos(0.3), 0.2 * math.sin(0.3), 0.1 * math.cos(1.1), 0.1 * math.sin(1.1)]
+    np.testing.assert_allclose(f, expect, rtol=1e-15, atol=1e-18)
+    np.testing.assert_allclose(F.features(b, K, A, [0.3, 1.1], [0.2, 0.1]), expect, rtol=1e-15, atol=1e-18)
+
+
+def test_bar_by_hand():
+    b = W.Body(np.array([[0, 0, 0], [1, 0, 0]]), np.array([0, 2], np.int32), np.array([-1, 1], np.int32))
+    f = _native([b], [0.0, 0.0], [0.0, 0.0])[0]
+    assert f[0] == pytest.approx(math.log(12))
+    assert f[1] == pytest.approx(math.log(2))
+    np.testing.assert_allclose(f[2:5], [2 * A, A, A])
+    np.testing.assert_allclose(f[5:8], [0.5, 0.0, 0.5])
+    np.testing.assert_allclose(f[8:11], 0.0, atol=1e-18)
+    assert f[11] == pytest.approx(A * A / 4)             # centres at +-a/2 about the mean
+    np.testing.assert_allclose(f[12:17], 0.0, atol=1e-18)
+    assert f[26] == 0.5
+    assert f[27] == pytest.approx(4.0)                     # mean of log10 1e3 and 1e5
+    # stiffness-weighted centre: (1e3 * a/2 + 1e5 * 3a/2) / (1e3 + 1e5) - a
+    assert f[28] == pytest.approx((1e3 * 0.5 * A + 1e5 * 1.5 * A) / (1e3 + 1e5) - A)
+    assert f[31] == pytest.approx(10 / 12)
+
+
+def test_native_matches_oracle_on_population():
+    w = W.population(12, seed=4, lo=300, hi=5000)
+    ph, am = W.population_actuation(4, 12, 32, draw=3)
+    nat = CR.cronos_features(w.bodies, W.MATERIAL_K, w.spacing, 32, ph, am)
+    for r, b in enumerate(w.bodies):
+        ora = F.features(b, W.MATERIAL_K, w.spacing, ph[32 * r:32 * (r + 1)], am[32 * r:32 * (r + 1)])
+        np.testing.assert_allclose(nat[r], ora, rtol=1e-11, atol=1e-15)
