@@ -47,6 +47,10 @@ typedef enum {
 #define CRONOS_NO_GRAPH       0x4u   /* enqueue steps as plain launches, not HIP graphs      */
 #define CRONOS_NO_TABLE       0x10u  /* keep explicit per-entry (k, L0) in the step instead of a
                                         16-bit index into the table of distinct pairs        */
+#define CRONOS_NO_SHIFT       0x20u  /* keep the caller's coordinate frame on the device (by
+                                        default a system without contact plane is shifted away
+                                        from the coordinate planes so plain differences are
+                                        exact; a system with contact is never shifted)        */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -287,6 +291,12 @@ cronos_status cronos_features(int32_t n_bodies, const int64_t* body_voxel_offset
                               const int32_t* material, const int32_t* group, int32_t n_materials,
                               const double* material_k, double spacing, int32_t n_groups, const double* phase,
                               const double* amp, double* out);
+
+/* Features of n_cand candidates that re-use already computed morphology descriptors:
+ * candidate c is robot body_of[c] (row of morph [n_bodies][32], from cronos_features with
+ * n_groups = 0) with its own actuation phase, amp [n_cand*n_groups]; out [n_cand][32+2 n_groups]. */
+cronos_status cronos_candidate_features(int64_t n_cand, const int32_t* body_of, int32_t n_bodies, const double* morph,
+                                        int32_t n_groups, const double* phase, const double* amp, double* out);
 
 /* Perceptron sizes[0] -> sizes[1] -> sizes[2] -> sizes[3] -> sizes[4] with exact-erf GELU
  * after the three hidden layers and a linear output.  Products on the BF16 matrix cores with

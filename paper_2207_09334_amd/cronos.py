@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcronos.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE = 0x1, 0x2, 0x4, 0x8, 0x10
+ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -102,6 +102,7 @@ _SIGS = {
     "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
     "cronos_rollout_backward": (C.c_int, [_p, _p, _p, _p, _p]),
     "cronos_features": (C.c_int, [_i32, _p, _p, _p, _p, _i32, _p, _f64, _i32, _p, _p, _p]),
+    "cronos_candidate_features": (C.c_int, [_i64, _p, _i32, _p, _i32, _p, _p, _p]),
     "cronos_mlp_create": (C.c_int, [_p, _p, _i32, _i32, _p, C.POINTER(_p)]),
     "cronos_mlp_destroy": (None, [_p]),
     "cronos_mlp_get_params": (C.c_int, [_p, _p]),
@@ -380,6 +381,16 @@ def cronos_features(bodies, material_k, spacing, n_groups, phase, amp) -> np.nda
     _check(_lib.cronos_features(len(bodies), _ptr(off), _ptr(vox), _ptr(mat), _ptr(grp),
                                 0 if mk is None else len(mk), _ptr(mk), spacing, n_groups, _ptr(ph), _ptr(am),
                                 _ptr(out)))
+    return out
+
+
+def cronos_candidate_features(body_of, morph, n_groups, phase, amp) -> np.ndarray:
+    bo = _arr(body_of, np.int32)
+    mo = _arr(morph, np.float64, (-1, 32))
+    ph, am = _arr(phase, np.float64), _arr(amp, np.float64)
+    out = np.empty((len(bo), 32 + 2 * n_groups))
+    _check(_lib.cronos_candidate_features(len(bo), _ptr(bo), len(mo), _ptr(mo), n_groups, _ptr(ph), _ptr(am),
+                                          _ptr(out)))
     return out
 
 

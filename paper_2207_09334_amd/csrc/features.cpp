@@ -128,3 +128,27 @@ extern "C" cronos_status cronos_features(int32_t n_bodies, const int64_t* body_v
     }
     return CRONOS_OK;
 }
+
+extern "C" cronos_status cronos_candidate_features(int64_t n_cand, const int32_t* body_of, int32_t n_bodies,
+                                                   const double* morph, int32_t n_groups, const double* phase,
+                                                   const double* amp, double* out) {
+    cronos::clear_error();
+    if (n_cand < 0 || n_bodies < 1 || !body_of || !morph || !out || n_groups < 0 || (n_groups && (!phase || !amp)))
+        return cronos::fail(CRONOS_EINVAL, "candidate_features: bad arguments");
+    for (int64_t c = 0; c < n_cand; ++c)
+        if (body_of[c] < 0 || body_of[c] >= n_bodies) return cronos::fail(CRONOS_EINVAL, "candidate_features: bad body index");
+    const int width = 32 + 2 * n_groups;
+    cronos::parallel_for(n_cand, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            double* f = out + c * width;
+            const double* m = morph + (int64_t)body_of[c] * 32;
+            for (int q = 0; q < 32; ++q) f[q] = m[q];
+            for (int g = 0; g < n_groups; ++g) {
+                const double A = amp[c * n_groups + g], ph = phase[c * n_groups + g];
+                f[32 + 2 * g] = A * std::cos(ph);
+                f[33 + 2 * g] = A * std::sin(ph);
+            }
+        }
+    }, 4096);
+    return CRONOS_OK;
+}

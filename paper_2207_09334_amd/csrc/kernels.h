@@ -13,6 +13,9 @@ struct StepParams {
     float ground_z, ground_k, ground_mu;
     int ground;          // contact plane on
     int exact;           // exact coordinate differences (see hooke in kernels.hip)
+    float safe;          // a wavefront whose masses all have |x_c| >= safe on every axis takes
+                         // the plain difference (Sterbenz-exact for springs shorter than safe/2)
+    double ox, oy, oz;   // origin of the device coordinates: absolute x = device x + o
 };
 
 // Device-resident layout and state of one simulation (all arrays in Morton order).

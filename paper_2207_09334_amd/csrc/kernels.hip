@@ -225,12 +225,22 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
     const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
     const float4 xi = sx[own];
     float fx, fy, fz;
-    if (TABLE)
-        gather_table<ACT, EXACT, BATCH>(sx, st, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.packed,
-                                        a.grp, a.factor, fx, fy, fz);
-    else
-        gather<ACT, EXACT, BATCH>(sx, xi, (base + (int)threadIdx.x) >> 6, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp,
-                                  a.factor, fx, fy, fz);
+    // Coordinates at least `safe` away from zero make every difference with a neighbour closer
+    // than safe/2 exact (Sterbenz), and a spring longer than that is far from rest, where a
+    // one-ulp error in d is negligible; such wavefronts skip the residual terms.
+    bool plain = !EXACT;
+    if (EXACT) {
+        const float m = fminf(fminf(fabsf(xi.x), fabsf(xi.y)), fabsf(xi.z));
+        plain = __builtin_amdgcn_ballot_w64(!(m >= p.safe)) == 0;
+    }
+    const int s = (base + (int)threadIdx.x) >> 6;
+    if (TABLE) {
+        if (plain) gather_table<ACT, false, BATCH>(sx, st, xi, s, a.nslice, a.slice_ptr, a.packed, a.grp, a.factor, fx, fy, fz);
+        else gather_table<ACT, true, BATCH>(sx, st, xi, s, a.nslice, a.slice_ptr, a.packed, a.grp, a.factor, fx, fy, fz);
+    } else {
+        if (plain) gather<ACT, false, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+        else gather<ACT, true, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+    }
     const int i = base + own;
     if (i >= a.n) return;
 
@@ -325,7 +335,12 @@ forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, co
     const int own = stage_positions(sx, xin, halo_ptr, halo_idx, lane_mass, b, base, n, block);
     const float4 xi = sx[own];
     float fx, fy, fz;
-    gather<ACT, true, 4>(sx, xi, (base + (int)threadIdx.x) >> 6, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    // the same choice of difference as the step, so this is the force the step integrates
+    const float mc = fminf(fminf(fabsf(xi.x), fabsf(xi.y)), fabsf(xi.z));
+    const bool plain = !p.exact || __builtin_amdgcn_ballot_w64(!(mc >= p.safe)) == 0;
+    const int s = (base + (int)threadIdx.x) >> 6;
+    if (plain) gather<ACT, false, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    else gather<ACT, true, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
     const int i = base + own;
     if (i >= n) return;
     const float m = mass[i];
@@ -408,12 +423,12 @@ diag_chunk_kernel(const float4* __restrict__ xin, const float* __restrict__ vin,
     acc[17] = 0.0;
     if (mine) {
         const double m = mass[i];
-        const double x = xi.x, y = xi.y, z = xi.z;
+        const double x = (double)xi.x + p.ox, y = (double)xi.y + p.oy, z = (double)xi.z + p.oz;
         const double vx = vin[3 * i], vy = vin[3 * i + 1], vz = vin[3 * i + 2];
         acc[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
         acc[2] = -m * ((double)p.gx * x + (double)p.gy * y + (double)p.gz * z);
         if (p.ground) {
-            const double pen = (double)p.ground_z - z;
+            const double pen = (double)p.ground_z - (double)xi.z;   // both in device coordinates
             if (pen > 0.0) acc[3] = 0.5 * (double)p.ground_k * pen * pen;
         }
         acc[4] = m * vx; acc[5] = m * vy; acc[6] = m * vz;
@@ -440,7 +455,8 @@ diag_chunk_kernel(const float4* __restrict__ xin, const float* __restrict__ vin,
                 double l0 = (double)c.y;
                 if (ACT) l0 *= (double)factor[grp[e]];
                 const float4 xj = sx[slot];
-                const double dx = (double)xj.x - x, dy = (double)xj.y - y, dz = (double)xj.z - z;
+                const double dx = (double)xj.x - (double)xi.x, dy = (double)xj.y - (double)xi.y,
+                             dz = (double)xj.z - (double)xi.z;
                 const double dl = sqrt(dx * dx + dy * dy + dz * dz) - l0;
                 es += 0.5 * (double)c.x * dl * dl;
             }

@@ -89,6 +89,8 @@ struct cronos_sim_t {
     std::vector<float> inv_m;            // new order
     std::vector<uint16_t> h_grp;         // per entry factor index (actuated sims), for the adjoint reduction
     std::vector<double> h_phase, h_amp;  // actuation parameters last set
+    double origin[3] = {0.0, 0.0, 0.0};  // absolute position = device position + origin
+    double rest_max = 0.0;               // longest nominal rest length
     RolloutBuffers ro;
     float4* h_x = nullptr;               // pinned staging
     float* h_v = nullptr;
@@ -389,6 +391,25 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         }
     }
 
+    // Device coordinates: without a contact plane, shifted so every mass starts at least
+    // `delta` (a power of two of at least twice the fast-path threshold) above zero on each
+    // axis, which lets nearly every wavefront take plain differences.  With the contact plane
+    // the user's frame is kept (the plane at device z = ground_z): penetrations of micrometres
+    // and stick/slip at the feet need the fine resolution FP32 has near the origin, and the
+    // shift would coarsen it; wavefronts near a coordinate plane take exact differences.
+    {
+        double rest_max = 0.0;
+        for (int64_t q = 0; q < s; ++q) rest_max = std::max(rest_max, d->rest[q]);
+        sim->rest_max = rest_max;
+        double delta = 1.0;
+        while (delta < 8.0 * rest_max) delta *= 2.0;
+        while (delta > 16.0 * rest_max && rest_max > 0.0) delta *= 0.5;
+        for (int c = 0; c < 3; ++c) {
+            double lo = xn[c];
+            for (int64_t i = 0; i < n; ++i) lo = std::min(lo, xn[3 * i + c]);
+            sim->origin[c] = (d->ground || (d->flags & CRONOS_NO_SHIFT)) ? 0.0 : lo - delta;
+        }
+    }
     std::vector<float4> hx(n);
     std::vector<float> hv(3 * n, 0.0f), hm(n), hf;
     sim->inv_m.resize(n);
@@ -396,7 +417,8 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         int32_t o = L.perm[i];
         float im = pin[i] ? 0.0f : (float)(1.0 / mn[i]);
         sim->inv_m[i] = im;
-        hx[i] = make_float4((float)xn[3 * i], (float)xn[3 * i + 1], (float)xn[3 * i + 2], im);
+        hx[i] = make_float4((float)(xn[3 * i] - sim->origin[0]), (float)(xn[3 * i + 1] - sim->origin[1]),
+                            (float)(xn[3 * i + 2] - sim->origin[2]), im);
         if (d->v0 && !pin[i])
             for (int c = 0; c < 3; ++c) hv[3 * i + c] = (float)d->v0[3 * o + c];
         hm[i] = (float)mn[i];
@@ -559,10 +581,14 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     P.gy = (float)d->gravity[1];
     P.gz = (float)d->gravity[2];
     P.ground = d->ground ? 1 : 0;
-    P.ground_z = (float)d->ground_z;
+    P.ground_z = (float)(d->ground_z - sim->origin[2]);
     P.ground_k = (float)d->ground_k;
     P.ground_mu = (float)d->ground_mu;
     P.exact = (d->flags & CRONOS_FAST_DIFF) ? 0 : 1;
+    P.safe = (float)(4.0 * sim->rest_max);
+    P.ox = sim->origin[0];
+    P.oy = sim->origin[1];
+    P.oz = sim->origin[2];
     if (persistent > 0) {
         int g = 0;
         hipError_t e = cronos::persistent_grid(D, P.exact, &g);
@@ -604,6 +630,14 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
     HIP_TRY(hipMemcpy(sim->d.phase, phase, m * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(sim->d.amp, amp, m * sizeof(double), hipMemcpyHostToDevice));
     sim->omega = 2.0 * M_PI * freq_hz;
+    double amax = 0.0;
+    for (size_t g = 0; g < m; ++g) amax = std::max(amax, std::fabs(amp[g]));
+    sim->p.safe = (float)(4.0 * sim->rest_max * (1.0 + amax));
+    for (auto& gr : sim->graph)   // graphs captured the old parameters
+        if (gr) {
+            (void)hipGraphExecDestroy(gr);
+            gr = nullptr;
+        }
     sim->h_phase.assign(phase, phase + m);
     sim->h_amp.assign(amp, amp + m);
     return CRONOS_OK;
@@ -641,9 +675,9 @@ extern "C" cronos_status cronos_read_state(cronos_sim sim, double* x, double* v,
     for (int64_t i = 0; i < n; ++i) {
         int32_t o = L.perm[i];
         if (x) {
-            x[3 * o + 0] = sim->h_x[i].x;
-            x[3 * o + 1] = sim->h_x[i].y;
-            x[3 * o + 2] = sim->h_x[i].z;
+            x[3 * o + 0] = (double)sim->h_x[i].x + sim->origin[0];
+            x[3 * o + 1] = (double)sim->h_x[i].y + sim->origin[1];
+            x[3 * o + 2] = (double)sim->h_x[i].z + sim->origin[2];
         }
         if (v)
             for (int c = 0; c < 3; ++c) v[3 * o + c] = sim->h_v[3 * i + c];
@@ -666,7 +700,8 @@ extern "C" cronos_status cronos_set_state(cronos_sim sim, const double* x, const
             int32_t o = L.perm[i];
             for (int c = 0; c < 3; ++c)
                 if (!std::isfinite(x[3 * o + c])) return fail(CRONOS_EINVAL, "set_state: non-finite x");
-            hx[i] = make_float4((float)x[3 * o], (float)x[3 * o + 1], (float)x[3 * o + 2], sim->inv_m[i]);
+            hx[i] = make_float4((float)(x[3 * o] - sim->origin[0]), (float)(x[3 * o + 1] - sim->origin[1]),
+                                (float)(x[3 * o + 2] - sim->origin[2]), sim->inv_m[i]);
         }
         HIP_TRY(hipMemcpy(sim->d.x[sim->cur], hx.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     }

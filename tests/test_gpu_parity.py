@@ -128,16 +128,17 @@ def test_positions_cube_contact_window():
 
 
 def test_positions_quadruped_1000():
-    """The actuated quadruped is sensitive: the FP64 oracle started from the FP32-rounded
-    initial state drifts from itself by ~3e-4 of the bbox by step 900.  The 1e-4 bar holds
-    over steps 0-400 (where that floor is ~1e-6); beyond, the device must stay within a small
-    multiple of the floor the dynamics themselves impose."""
+    """The actuated quadruped is sensitive: the FP64 oracle started from the device's own FP32
+    initial state drifts from the exact start by ~3e-4 of the bbox by step 900.  The 1e-4 bar
+    holds over steps 0-400 (where that floor is ~1e-6); beyond, the device must stay within a
+    small multiple of the floor the dynamics themselves impose on its representation."""
     w = W.quadruped()
     say("case: quadruped steps 0-1000 (actuated, contact) vs the sensitivity floor")
     lat, sys_, x0 = oracle_problem(w)
     sim, _, _ = PR.create(w, x0=x0, flags=CR.CHECK_LAYOUT)
+    x_dev0, _, _ = CR.cronos_read_state(sim)          # the device's FP32 start, widened
     xa, va = x0.copy(), np.zeros_like(x0)
-    xb, vb = x0.astype(np.float32).astype(np.float64), np.zeros_like(x0)
+    xb, vb = x_dev0.copy(), np.zeros_like(x0)
     for n in range(0, 1000, 100):
         xa, va = P.run(sys_, xa, va, n, 100)
         xb, vb = P.run(sys_, xb, vb, n, 100)
@@ -182,6 +183,7 @@ def test_population_full_size_sampled():
     w = W.population(1024)
     say("case: population 1024 robots, 300 steps, robots 0/511/1023 re-simulated by the oracle")
     sim, lat, x0 = PR.create(w)
+    x0_dev, _, _ = CR.cronos_read_state(sim)
     info = CR.cronos_info(sim)
     say(f"  {info['n_masses']} masses, {info['n_springs']} springs")
     CR.cronos_step(sim, 300)
@@ -194,7 +196,7 @@ def test_population_full_size_sampled():
         assert e - s == olat.n_masses
         assert np.array_equal(x0[s:e], ox0)
         xa, va = P.run(osys, ox0.copy(), np.zeros_like(ox0), 0, 300)
-        xb, vb = P.run(osys, ox0.astype(np.float32).astype(np.float64), np.zeros_like(ox0), 0, 300)
+        xb, vb = P.run(osys, x0_dev[s:e], np.zeros_like(ox0), 0, 300)
         err, floor = position_error(xg[s:e], xa), position_error(xb, xa)
         say(f"  robot {r}: {e - s} masses, err {err:.3e}, floor {floor:.3e}")
         assert err <= max(X_TOL, 30.0 * floor)
@@ -296,15 +298,36 @@ def test_ragged_and_tiny_systems():
 def test_pinned_masses_do_not_move_and_state_roundtrip():
     w = W.cantilever(20, 4, 4)
     sim, lat, x0 = PR.create(w)
+    xs, _, _ = CR.cronos_read_state(sim)
+    pin = lat.pinned.astype(bool)
+    np.testing.assert_allclose(xs, x0, rtol=0, atol=1e-7)         # FP32 storage of the input
     CR.cronos_step(sim, 257)
     x, v, step = CR.cronos_read_state(sim)
-    pin = lat.pinned.astype(bool)
     assert step == 257
-    assert np.array_equal(x[pin], x0[pin].astype(np.float32).astype(np.float64))
+    assert np.array_equal(x[pin], xs[pin])
     assert (v[pin] == 0).all()
     CR.cronos_set_state(sim, x, v, 257)
     x2, v2, _ = CR.cronos_read_state(sim)
     assert np.array_equal(x2, x) and np.array_equal(v2, v)
+
+
+def test_far_from_origin_and_near_plane_accuracy():
+    """The same strained cube placed far from the origin, straddling the coordinate planes,
+    and with the plain-difference fast path forced off: per-step forces meet the bar in every
+    placement (the device chooses exact differences wherever coordinates come near zero)."""
+    base = W.cube_drop(6)
+    for origin in ((0.0, 0.0, 0.05), (-0.03, -0.02, 0.05), (37.0, -12.5, 0.05)):
+        w = W.Workload(**{**base.__dict__, "origin": origin})
+        lat, sys_, x0 = oracle_problem(w)
+        for flags in (0, CR.FAST_DIFF):
+            sim, _, _ = PR.create(w, x0=x0, flags=flags)
+            CR.cronos_step(sim, 200)
+            xg, _, _ = CR.cronos_read_state(sim)
+            e, _ = force_error(CR.cronos_eval_forces(sim), sys_, xg, 200 * w.dt)
+            say(f"  origin {origin} flags {flags}: force err {e:.2e}")
+            if flags == 0:
+                assert e <= F_TOL
+            sim.close()
 
 
 def test_layout_of_created_sim_matches_oracle():
