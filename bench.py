@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spring-steps/sec + % HBM roofline; surrogate vs plain sim evals/sec"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK = 256 * 2.4e9          # wave64 VALU instructions per second: 256 CUs x 2.4 GHz x 1 per CU
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cantilever_400x40x40.traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_09334_amd", "csrc", "kernels.hip")
 
@@ -47,16 +48,19 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
-def measured_traffic(steps_per_launch: int = 1):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary, or None
-    when the kernel source changed since the counters were taken."""
+def profile_record(workload: str, launch: dict):
+    """The committed rocprofv3 counter summary of the step kernel (HBM bytes and VALU
+    instructions per launch), or None when it was taken for another workload or launch
+    configuration, or before the kernel source last changed."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_sha256") != kernel_source_hash():
+    if rec.get("kernels_sha256") != kernel_source_hash() or rec.get("workload") != workload:
         return None
-    return float(rec["hbm_bytes_per_launch"])
+    if any(rec.get(k) != launch.get(k) for k in ("block_masses", "batch", "persistent_groups", "step_form")):
+        return None
+    return rec
 
 
 def cpu_baseline(workload, steps: int):
@@ -84,42 +88,53 @@ def cpu_baseline(workload, steps: int):
 
 
 def surrogate_bench(args) -> dict:
-    """Surrogate screening vs the plain batched simulator.  A pool of robots (seed 4) is
-    simulated under `draws` actuation draws (5000 steps each); the first 7/8 of the robots
-    train the network, the last 1/8 are held-out candidates judged by the simulator."""
+    """Surrogate screening vs the plain batched simulator.  Morphology pools of `pool` robots
+    (seed 4, disjoint robot-index ranges) are each simulated under `draws` actuation draws
+    (5000 steps each); the robots of the first `pools` pools train the network, those of the
+    next `held_pools` pools are held-out candidates judged by the simulator."""
     import numpy as np
 
+    from paper_2207_09334_amd import cronos as CR
     from paper_2207_09334_amd import surrogate as SG
 
-    pool = SG.Pool(args.pool, seed=4, steps=5000)
-    n_train_robots = args.pool * 7 // 8
-    Xtr, Dtr, Xte, Dte, acts = [], [], [], [], []
-    for d in range(args.draws):
-        X, D = pool.draw(d)
-        Xtr.append(X[:n_train_robots])
-        Dtr.append(D[:n_train_robots])
-        Xte.append(X[n_train_robots:])
-        Dte.append(D[n_train_robots:])
-        acts.append(pool.actuation(d))
-    sim_rate = pool.rollouts_done / pool.sim_seconds
-    # the simulator's own noise floor on this target: draw 0 again with every phase moved by
-    # 1e-6 rad; the chaotic part of the displacement is beyond any predictor
-    ph0, am0 = pool.actuation(0)
-    D0p = pool.rollout(ph0 + 1e-6, am0)
-    noise_floor = SG.rms_relative_error(D0p, np.concatenate([Dtr[0], Dte[0]]))
+    G = 32
+    Xtr, Dtr, Xte, Dte = [], [], [], []
+    held_bodies, ph_c, am_c, body_of = [], [], [], []
+    sim_seconds, rollouts, noise_floor = 0.0, 0, None
+    material_k = spacing = None
+    for p in range(args.pools + args.held_pools):
+        pool = SG.Pool(args.pool, seed=4, steps=5000, first_robot=p * args.pool)
+        material_k, spacing = pool.workload.material_k, pool.workload.spacing
+        held = p >= args.pools
+        for d in range(args.draws):
+            X, D = pool.draw(d)
+            (Xte if held else Xtr).append(X)
+            (Dte if held else Dtr).append(D)
+            if held:
+                ph, am = pool.actuation(d)
+                ph_c.append(ph)
+                am_c.append(am)
+                body_of.append(np.arange(args.pool, dtype=np.int32) + len(held_bodies))
+        if p == 0:
+            # the simulator's own noise floor on this target: draw 0 again with every phase
+            # moved by 1e-6 rad; the chaotic part of the displacement is beyond any predictor
+            ph0, am0 = pool.actuation(0)
+            noise_floor = SG.rms_relative_error(pool.rollout(ph0 + 1e-6, am0), Dtr[0])
+        if held:
+            held_bodies.extend(pool.workload.bodies)
+        sim_seconds += pool.sim_seconds
+        rollouts += pool.rollouts_done
+        pool.close()
+        print(f"surrogate: pool {p} done ({'held-out' if held else 'training'})", file=sys.stderr, flush=True)
+    sim_rate = rollouts / sim_seconds
     Xtr, Dtr, Dte = np.concatenate(Xtr), np.concatenate(Dtr), np.concatenate(Dte)
     sur = SG.Surrogate(Xtr, Dtr, epochs=args.epochs, batch=1024)
     # screening throughput: candidates are (robot, actuation) pairs; the robots' morphology
     # descriptors are computed once, each candidate's features assembled natively, then predicted
-    from paper_2207_09334_amd import cronos as CR
-    held = pool.workload.bodies[n_train_robots:]
-    G = 32
-    n_held = len(held)
-    body_of = np.tile(np.arange(n_held, dtype=np.int32), len(acts))
-    ph_c = np.concatenate([ph.reshape(args.pool, G)[n_train_robots:] for ph, _ in acts]).ravel()
-    am_c = np.concatenate([am.reshape(args.pool, G)[n_train_robots:] for _, am in acts]).ravel()
+    body_of = np.concatenate(body_of)
+    ph_c, am_c = np.concatenate(ph_c), np.concatenate(am_c)
     t0 = time.perf_counter()
-    morph = CR.cronos_features(held, pool.workload.material_k, pool.workload.spacing, 0, None, None)
+    morph = CR.cronos_features(held_bodies, material_k, spacing, 0, None, None)
     Xc = CR.cronos_candidate_features(body_of, morph, G, ph_c, am_c)
     pred = sur.predict(Xc)
     flagged = sur.out_of_distribution(Xc)
@@ -137,7 +152,8 @@ def surrogate_bench(args) -> dict:
     return {
         "metric": "surrogate vs plain sim evals/sec", "value": sur_rate / sim_rate, "unit": "x",
         "higher_is_better": True, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
-        "config": {"workload": f"surrogate_pool{args.pool}_draws{args.draws}", "rollout_steps": 5000,
+        "config": {"workload": f"surrogate_{args.pools}x{args.pool}robots_draws{args.draws}", "rollout_steps": 5000,
+                   "heldout_robots": args.held_pools * args.pool,
                    "train_rollouts": int(len(Xtr)), "heldout_candidates": int(n_cand), "epochs": args.epochs},
         "surrogate_evals_per_s": sur_rate, "sim_evals_per_s": sim_rate,
         "rms_rel_error": err, "p95_rel_error": float(np.percentile(per, 95)),
@@ -155,15 +171,19 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0, help="entries loaded ahead per lane (2, 4 or 8; 0 = default)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--fast-diff", action="store_true", help="skip the exact coordinate difference")
     ap.add_argument("--no-table", action="store_true", help="explicit per-entry (k, L0) instead of the table")
+    ap.add_argument("--split", action="store_true", help="split step form (spring pass + gather pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
     ap.add_argument("--workload", choices=("cantilever", "population", "surrogate"), default="cantilever")
-    ap.add_argument("--pool", type=int, default=2048, help="surrogate: robots in the morphology pool")
-    ap.add_argument("--draws", type=int, default=40, help="surrogate: actuation draws simulated per robot")
+    ap.add_argument("--pool", type=int, default=1024, help="surrogate: robots per morphology pool")
+    ap.add_argument("--pools", type=int, default=8, help="surrogate: training pools (disjoint robots)")
+    ap.add_argument("--held-pools", type=int, default=1, help="surrogate: held-out pools")
+    ap.add_argument("--draws", type=int, default=8, help="surrogate: actuation draws simulated per robot")
     ap.add_argument("--epochs", type=int, default=60, help="surrogate: training epochs")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
@@ -194,8 +214,8 @@ def main():
     lat = PR.build_lattice(w)
     stream = torch.cuda.Stream()
     flags = ((CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0) |
-             (CR.NO_TABLE if args.no_table else 0))
-    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
+             (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0))
+    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block, batch=args.batch,
                           tune_steps=20 if args.tune else 0)
     info = CR.cronos_info(sim)
     launch = CR.cronos_launch_config(sim)
@@ -203,12 +223,24 @@ def main():
     batched = len(w.bodies) > 1
     actuated = w.n_groups > 0
 
+    copy_gbs = None
     if args.calibrate_copy:
+        # a plain device-to-device copy of known size: the reference for the byte counters and
+        # the bandwidth a streaming kernel reaches on this device (best of 5)
         src = torch.ones(args.calibrate_copy * (1 << 18), dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = None
         with torch.cuda.stream(stream):
-            dst.copy_(src)
+            for _ in range(5):
+                e0.record(stream)
+                dst.copy_(src)
+                e1.record(stream)
+                e1.synchronize()
+                t = e0.elapsed_time(e1)
+                best = t if best is None else min(best, t)
         torch.cuda.synchronize()
+        copy_gbs = 2.0 * src.numel() * 4 / (best / 1e3) / 1e9
         del src, dst
     torch.cuda.synchronize()
     CR.cronos_step(sim, args.warmup)
@@ -232,7 +264,8 @@ def main():
     value = S / sec_per_step
     b_step = algorithmic_bytes(N, S, actuated=actuated, batched=batched)
     achieved = b_step / sec_per_step / 1e9
-    traffic = measured_traffic()
+    prof = profile_record(w.name, launch)
+    traffic = float(prof["hbm_bytes_per_launch"]) if prof else None
     out = {
         "metric": METRIC, "value": value, "unit": "spring-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -240,11 +273,20 @@ def main():
         "config": {"workload": w.name, "n_bodies": len(w.bodies), "n_masses": N, "n_springs": S, "dt": w.dt,
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
                    "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
-                   "exact_difference": not args.fast_diff, "parameter_table": not args.no_table},
+                   "exact_difference": not args.fast_diff, "step_form": launch["step_form"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": b_step},
     }
+    if copy_gbs is not None:
+        out["roofline"]["copy_kernel_gbs"] = copy_gbs
+        out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    if prof and prof.get("valu_wave_instr_per_launch"):
+        # the step's other ceiling: VALU issue, one wave64 instruction per cycle per CU
+        # (non-packed FP32), from the committed SQ_INSTS_VALU count of this configuration
+        rate = prof["valu_wave_instr_per_launch"] / sec_per_step
+        out["valu_issue"] = {"achieved": rate, "peak": VALU_PEAK, "unit": "wave64 VALU instr/s",
+                             "frac": rate / VALU_PEAK, "instr_per_launch": prof["valu_wave_instr_per_launch"]}
     if batched:
         out["rollouts_per_s"] = len(w.bodies) / (w.steps * sec_per_step)
         out["rollout_steps"] = w.steps

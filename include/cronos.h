@@ -48,9 +48,12 @@ typedef enum {
 #define CRONOS_NO_TABLE       0x10u  /* keep explicit per-entry (k, L0) in the step instead of a
                                         16-bit index into the table of distinct pairs        */
 #define CRONOS_NO_SHIFT       0x20u  /* keep the caller's coordinate frame on the device (by
-                                        default a system without contact plane is shifted away
-                                        from the coordinate planes so plain differences are
-                                        exact; a system with contact is never shifted)        */
+                                        default it is shifted away from the coordinate planes
+                                        so plain differences are exact; z is never shifted
+                                        when the contact plane is on)                        */
+#define CRONOS_SPLIT          0x40u  /* split step form: a spring pass evaluates each spring once
+                                        per workgroup into LDS, then a gather pass sums them
+                                        (default: every spring evaluated from both ends)    */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -234,8 +237,14 @@ cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);
 /* Information on the simulation: masses, springs, bodies, groups, steps taken, block size. */
 cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
                           int32_t* block_masses, int64_t* step);
-/* Launch configuration in use: batch, persistent workgroups (0 = one per block). */
-cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups);
+/* Launch configuration in use: masses per workgroup, batch, persistent workgroups (0 = one
+ * per block) and the form of the step's incidence data (CRONOS_FORM_*).  Any output may be
+ * NULL. */
+#define CRONOS_FORM_EXPLICIT 0  /* (slot, k, L0) per entry, every spring evaluated at both ends  */
+#define CRONOS_FORM_TABLE    1  /* 32-bit entries indexing the table of distinct (k, L0) pairs    */
+#define CRONOS_FORM_SPLIT    2  /* spring pass (each spring once per workgroup) + gather pass     */
+cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
+                                   int32_t* step_form);
 
 /* Launch configuration chosen by the autotuner for a problem. */
 typedef struct {

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcronos.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -97,7 +97,7 @@ _SIGS = {
     "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
                               C.POINTER(_i64)]),
     "cronos_get_layout": (C.c_int, [_p] * 6),
-    "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
     "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
     "cronos_rollout_backward": (C.c_int, [_p, _p, _p, _p, _p]),
@@ -278,10 +278,13 @@ def cronos_autotune(x0, mass, ends, k, rest, n_steps=20, **kw) -> dict:
     return cronos_create(x0, mass, ends, k, rest, _tune_steps=n_steps, **kw)
 
 
+FORMS = ("explicit", "table", "split")
+
+
 def cronos_launch_config(sim: Sim) -> dict:
-    b, bt, pg = _i32(), _i32(), _i32()
-    _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg)))
-    return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value}
+    b, bt, pg, fm = _i32(), _i32(), _i32(), _i32()
+    _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg), C.byref(fm)))
+    return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value, "step_form": FORMS[fm.value]}
 
 
 def cronos_destroy(sim: Sim):

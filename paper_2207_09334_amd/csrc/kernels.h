@@ -36,17 +36,25 @@ struct DeviceArrays {
     uint16_t* nbr = nullptr;
     float2* kl = nullptr;                // (k, L0) per entry
     uint32_t* packed = nullptr;          // compact entries: LDS slot | table index << 16 (or null)
-    float2* table = nullptr;             // distinct (k, L0) pairs of the compact entries
+    float4* table = nullptr;             // distinct (k, L0) pairs of the compact entries, as
+                                         // (k, L0, fl(L0^2), L0^2 - fl(L0^2))
     int32_t n_table = 0;
+    int2* blk_groups = nullptr;          // per workgroup (first factor index, count) of its actuated springs
+    int32_t max_local_groups = 0;
+    uint32_t* sp_rec = nullptr;          // split form (see the step kernel): spring records,
+    uint16_t* sp_grp = nullptr;          //   their local actuation factor indices,
+    int32_t* sp_ptr = nullptr;           //   per-workgroup record ranges
+    int32_t max_sp = 0;                  //   and the largest record count of a workgroup
     uint16_t* grp = nullptr;             // per entry index into factor[], or null
     int32_t* halo_ptr = nullptr;
     int32_t* halo_idx = nullptr;
     // actuation
     int32_t n_factor = 0;                // bodies * groups (factor[n_factor] = 1 for passive)
-    double* phase = nullptr;
-    double* amp = nullptr;
+    float* phase = nullptr;
+    float* amp = nullptr;
     float* factor = nullptr;             // 1 + A sin(...) per (body, group), FP32
     long long* step_ctr = nullptr;       // device step counter n
+    unsigned* act_done = nullptr;        // workgroups of the actuation launch that have finished
     // diagnostics
     int32_t n_chunks = 0;
     int32_t nb = 1;
@@ -59,6 +67,12 @@ struct DeviceArrays {
 
 constexpr int kDiagFields = 20;  // ke, pe_s, pe_g, pe_c, p3, mx3, mass, min3, max3, nonfinite
 
+// Byte address of the parameter table in a step workgroup's LDS: after the positions, rounded
+// up to a multiple of 8192 so that OR-ing an in-table offset (< 8192) adds it.
+__host__ __device__ inline uint32_t table_base(int lds_slots) { return ((uint32_t)lds_slots * 16u + 8191u) & ~8191u; }
+// Static LDS of the step kernels (must be 0: entry words carry absolute LDS byte addresses).
+hipError_t step_static_lds(size_t* bytes);
+
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 // The step with explicit buffers; vstar (optional) receives the velocity before friction/damping.
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
@@ -66,8 +80,9 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
 // Workgroups of a persistent launch that are resident at once on the device (multiple of 8).
 hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid);
 // Actuation table for the device step counter (advancing it when advance != 0), or for the
-// explicit step n_explicit >= 0 (counter untouched).
-hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st,
+// explicit step n_explicit >= 0 (counter untouched).  cycles = frac(f dt) * 2^64, the part of
+// an actuation period that one step advances, in 64-bit fixed point.
+hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
                             long long n_explicit = -1);
 // Adjoint of one step (see kernels.hip).
 hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,

@@ -32,11 +32,13 @@ __device__ __forceinline__ int logical_block(int nblk) {
     return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
 }
 
-// Error-free sum (Knuth): s + e == a + b exactly.
-__device__ __forceinline__ float two_sum(float a, float b, float& e) {
-    float s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
+// Coordinate-difference modes of the spring arithmetic (see hooke_fac).
+enum : int { kPlain = 0, kExactZ = 1, kExactAll = 2 };
+
+// Error-free sum of a and b when |a| >= |b| (Dekker's Fast2Sum): s + e == a + b exactly.
+__device__ __forceinline__ float fast_two_sum(float a, float b, float& e) {
+    const float s = a + b;
+    e = b - (s - a);
     return s;
 }
 
@@ -47,46 +49,82 @@ __device__ __forceinline__ float sub_residual(float a, float b, float s) {
     return (a - (s - bb)) - (b + bb);
 }
 
-// Hooke force of eq. (2) on mass i from one spring to a neighbour at (xj, yj, zj),
-// accumulated into f; a zero-length spring contributes zero.
-// EXACT: d = xj - xi is exact whenever the two coordinates are within a factor of two of
-// each other (Sterbenz); near a coordinate plane it is not, and for a nearly relaxed spring
-// that one-ulp error in d would be a large fraction of the elongation.  With EXACT the
-// subtraction residuals r are folded into |d|^2 - L0^2 (as 2 d r), so the elongation is that
-// of the stored positions whatever their magnitude.
-template <bool EXACT>
-__device__ __forceinline__ void hooke(float xi, float yi, float zi, float xj, float yj, float zj,
-                                      float k, float l0, float& fx, float& fy, float& fz) {
-    const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+// Scalar factor of the Hooke force of eq. (2) for the spring from (xi, yi, zi) to (xj, yj, zj):
+// the force on the first end is fac * d with d = xj - xi; a zero-length spring gives 0 (its d
+// is 0 and fac stays finite).  Every step below is unchanged, bit for bit, when d changes sign,
+// so both ends of a spring see the same factor.
+//
+// Elongation: |d| - L0 = (|d|^2 - L0^2) / (|d| + L0), with |d|^2 - L0^2 formed from error-free
+// pieces: squares by FMA (dx^2 = px + ex exactly), their sum by Fast2Sum on the three squares
+// sorted by size (max3 / med3 / min3), and L0^2 = q + eq.  Near rest the leading difference
+// s2 - q is exact, so the error is a few ulps of the elongation itself, not of L0.
+// EX: d = xj - xi is exact whenever the two coordinates are within a factor of two of each
+// other (Sterbenz); near a coordinate plane it is not, and for a nearly relaxed spring that
+// one-ulp error in d would be a large fraction of the elongation.  kExactAll folds the
+// subtraction residuals r in (|d + r|^2 = |d|^2 + 2 d.r + O(r^2)), so the elongation is that
+// of the stored positions whatever their magnitude; kExactZ does so for z only, for
+// wavefronts near the z = 0 plane alone (the contact plane); kPlain skips them.
+template <int EX>
+__device__ __forceinline__ float hooke_fac(float xi, float yi, float zi, float xj, float yj, float zj, float k,
+                                           float l0, float q, float eq, float& dx, float& dy, float& dz) {
+    dx = xj - xi;
+    dy = yj - yi;
+    dz = zj - zi;
     const float px = dx * dx, py = dy * dy, pz = dz * dz;
     const float ex = __builtin_fmaf(dx, dx, -px);
     const float ey = __builtin_fmaf(dy, dy, -py);
     const float ez = __builtin_fmaf(dz, dz, -pz);
-    const float q = l0 * l0;
-    const float eq = __builtin_fmaf(l0, l0, -q);
+    const float big = __builtin_fmaxf(__builtin_fmaxf(px, py), pz);
+    const float mid = __builtin_amdgcn_fmed3f(px, py, pz);
+    const float small = __builtin_fminf(__builtin_fminf(px, py), pz);
     float e1, e2;
-    const float s1 = two_sum(px, py, e1);
-    const float s2 = two_sum(s1, pz, e2);
-    // |d|^2 - L0^2 = (s2 - q) + (e1 + e2 + ex + ey + ez - eq); s2 - q is exact near rest
+    const float s1 = fast_two_sum(big, mid, e1);
+    const float s2 = fast_two_sum(s1, small, e2);
+    // |d|^2 - L0^2 = (s2 - q) + (e1 + e2 + ex + ey + ez - eq)
     float lo = ((e1 + e2) + (ex + ey)) + (ez - eq);
-    if (EXACT) {
+    if (EX == kExactAll) {
         const float rx = sub_residual(xj, xi, dx);
         const float ry = sub_residual(yj, yi, dy);
         const float rz = sub_residual(zj, zi, dz);
-        lo = __builtin_fmaf(dx + dx, rx, lo);
-        lo = __builtin_fmaf(dy + dy, ry, lo);
-        lo = __builtin_fmaf(dz + dz, rz, lo);
+        const float dr = __builtin_fmaf(dz, rz, __builtin_fmaf(dy, ry, dx * rx));
+        lo = __builtin_fmaf(2.0f, dr, lo);
+    } else if (EX == kExactZ) {  // x and y differences are exact (their residuals are 0)
+        lo = __builtin_fmaf(2.0f, dz * sub_residual(zj, zi, dz), lo);
     }
     const float diff = (s2 - q) + lo;
     const float len = __builtin_amdgcn_sqrtf(s2);
-    const float den = (len + l0) * len;
-    // computed unconditionally and then selected, so a zero length (padding entries) costs
-    // no branch; the NaN of 0 * rcp(0) is discarded by the select
-    float fac = k * diff * __builtin_amdgcn_rcpf(den);
-    fac = len > 0.0f ? fac : 0.0f;
+    // |d| (|d| + L0) = s2 + L0 |d| to within an ulp; the floor keeps a zero-length spring's
+    // factor finite (its force fac * d is then exactly 0) and is far below any real spring's
+    const float den = __builtin_fmaxf(__builtin_fmaf(l0, len, s2), 1e-30f);
+    return k * diff * __builtin_amdgcn_rcpf(den);
+}
+
+// Hooke force of eq. (2) on mass i from one spring to a neighbour at (xj, yj, zj),
+// accumulated into f.
+template <int EX>
+__device__ __forceinline__ float hooke_fac(float xi, float yi, float zi, float xj, float yj, float zj, float k,
+                                           float l0, float& dx, float& dy, float& dz) {
+    const float q = l0 * l0;
+    return hooke_fac<EX>(xi, yi, zi, xj, yj, zj, k, l0, q, __builtin_fmaf(l0, l0, -q), dx, dy, dz);
+}
+
+template <int EX>
+__device__ __forceinline__ void hooke(float xi, float yi, float zi, float xj, float yj, float zj,
+                                      float k, float l0, float& fx, float& fy, float& fz) {
+    float dx, dy, dz;
+    const float fac = hooke_fac<EX>(xi, yi, zi, xj, yj, zj, k, l0, dx, dy, dz);
     fx = __builtin_fmaf(fac, dx, fx);
     fy = __builtin_fmaf(fac, dy, fy);
     fz = __builtin_fmaf(fac, dz, fz);
+}
+
+// The same with a parameter-table entry c = (k, L0, L0^2, its FMA residual); an actuated spring
+// scales L0 by its factor g and squares it here.
+template <bool ACT, int EX>
+__device__ __forceinline__ float hooke_fac_tab(float4 xi, float4 xj, float4 c, float g, float& dx, float& dy,
+                                               float& dz) {
+    if (ACT) return hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, c.y * g, dx, dy, dz);
+    return hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, c.y, c.z, c.w, dx, dy, dz);
 }
 
 // Stage the workgroup's masses (in mass order) and its halo in LDS; returns the block-relative
@@ -110,7 +148,7 @@ __device__ __forceinline__ int stage_positions(float4* __restrict__ sx, const fl
 // Sum of the spring forces on this lane's mass over its slice entries.  The slice (and so the
 // trip count) is uniform across the wavefront; entries are fetched in batches of BATCH so
 // that several loads are in flight before the first is consumed.
-template <bool ACT, bool EXACT, int BATCH>
+template <bool ACT, int EX, int BATCH>
 __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi, int s, int nslice,
                                        const int32_t* __restrict__ slice_ptr,
                                        const uint16_t* __restrict__ nbr, const float2* __restrict__ kl,
@@ -140,7 +178,7 @@ __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi,
         for (int u = 0; u < BATCH; ++u) {
             const float4 xj = sx[slot[u]];
             const float l0 = ACT ? c[u].y * f[u] : c[u].y;
-            hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c[u].x, l0, fx, fy, fz);
+            hooke<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c[u].x, l0, fx, fy, fz);
         }
     }
     for (; r < w; ++r) {
@@ -148,18 +186,49 @@ __device__ __forceinline__ void gather(const float4* __restrict__ sx, float4 xi,
         const float2 c = pk[r * 64];
         const float l0 = ACT ? c.y * factor[pg[r * 64]] : c.y;
         const float4 xj = sx[slot];
-        hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
+        hooke<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
     }
 }
 
-// The same sum over the compact entry stream: one 32-bit word per entry holding the LDS slot
-// (low 16 bits) and the index of the spring's (k, L0) pair in the simulation's parameter
-// table (high 16 bits), the table being staged in LDS (st).
-template <bool ACT, bool EXACT, int BATCH>
-__device__ __forceinline__ void gather_table(const float4* __restrict__ sx, const float2* __restrict__ st, float4 xi,
-                                             int s, int nslice, const int32_t* __restrict__ slice_ptr,
-                                             const uint32_t* __restrict__ packed, const uint16_t* __restrict__ grp,
-                                             const float* __restrict__ factor, float& fx, float& fy, float& fz) {
+// LDS read at a byte address.  The step kernels declare no static LDS, so their dynamic LDS
+// (positions first) starts at address 0 (checked on the host) and an entry word can carry
+// ready-made byte addresses.
+typedef float lds_vec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 lds_f4(uint32_t byte) {
+    const lds_vec4 v = *(const __attribute__((address_space(3))) lds_vec4*)(size_t)byte;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float lds_f1(uint32_t byte) {
+    return *(const __attribute__((address_space(3))) float*)(size_t)byte;
+}
+
+// The same sum over the compact entry stream: one 32-bit word per entry and the parameter
+// table of the simulation's distinct (k, L0) pairs staged in LDS at byte address T (a
+// multiple of 8192, so "| T" adds it).
+//   passive simulations: neighbour slot << 19 | pair index << 4, so the neighbour's byte
+//     address is q >> 15 and the pair's is (q & 0x1FF0) | T;
+//   actuated simulations: neighbour slot (bits 0-12) | pair index (bits 13-21) | index of
+//     the spring's actuation factor in the workgroup's slice of the factor table, staged in
+//     LDS at sf (bits 22-31, 0 = passive).
+constexpr uint32_t kSlotBits = 13, kTypeBits = 9;
+
+template <bool ACT>
+__device__ __forceinline__ void decode_entry(uint32_t q, uint32_t tbase, uint32_t& xa, uint32_t& ca, uint32_t& g) {
+    if (ACT) {
+        xa = (q & ((1u << kSlotBits) - 1u)) << 4;
+        ca = ((q >> (kSlotBits - 4)) & (((1u << kTypeBits) - 1u) << 4)) | tbase;
+        g = q >> (kSlotBits + kTypeBits);
+    } else {
+        xa = q >> 15;
+        ca = (q & (((1u << kTypeBits) - 1u) << 4)) | tbase;
+        g = 0;
+    }
+}
+
+template <bool ACT, int EX, int BATCH>
+__device__ __forceinline__ void gather_table(uint32_t tbase, const float* __restrict__ sf, float4 xi, int s,
+                                             int nslice, const int32_t* __restrict__ slice_ptr,
+                                             const uint32_t* __restrict__ packed, float& fx, float& fy, float& fz) {
     fx = fy = fz = 0.0f;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s >= nslice) return;
@@ -167,31 +236,124 @@ __device__ __forceinline__ void gather_table(const float4* __restrict__ sx, cons
     const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
     const int w = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
     const uint32_t* pp = packed + e0 + lane;
-    const uint16_t* pg = ACT ? grp + e0 + lane : nullptr;
+    auto one = [&](uint32_t q) {
+        uint32_t xa, ca, gi;
+        decode_entry<ACT>(q, tbase, xa, ca, gi);
+        const float4 xj = lds_f4(xa);
+        const float4 c = lds_f4(ca);
+        const float g = ACT ? sf[gi] : 1.0f;
+        float dx, dy, dz;
+        const float fac = hooke_fac_tab<ACT, EX>(xi, xj, c, g, dx, dy, dz);
+        fx = __builtin_fmaf(fac, dx, fx);
+        fy = __builtin_fmaf(fac, dy, fy);
+        fz = __builtin_fmaf(fac, dz, fz);
+    };
     int r = 0;
     for (; r + BATCH <= w; r += BATCH) {
         uint32_t q[BATCH];
-        float f[BATCH];
 #pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            q[u] = pp[(r + u) * 64];
-            if (ACT) f[u] = factor[pg[(r + u) * 64]];
+        for (int u = 0; u < BATCH; ++u) q[u] = pp[(r + u) * 64];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) one(q[u]);
+    }
+    for (; r < w; ++r) one(pp[r * 64]);
+}
+
+// Split form of the same sum, in two passes over the workgroup's LDS.
+// Spring pass: every spring with an end among the workgroup's masses is evaluated once (a
+// spring between two of them is shared; one to a halo mass is evaluated here and again by
+// the workgroup that owns the other end), its force factor stored in LDS (sfac).  Record
+// word: LDS slot of the first end (bits 0-9, always a workgroup mass), LDS slot of the other
+// end (bits 10-22), (k, L0) pair index (bits 23-31); actuated springs carry their local
+// factor index in a parallel 16-bit stream.
+constexpr uint32_t kRecA = 10, kRecB = 13;
+
+template <bool ACT, bool EXACT, int BATCH>
+__device__ __forceinline__ void spring_pass(const float4* __restrict__ sx, uint32_t tbase,
+                                            const float* __restrict__ sf, float* __restrict__ sfac,
+                                            const uint32_t* __restrict__ rec, const uint16_t* __restrict__ rgrp,
+                                            int n_sp, int block, float safe) {
+    const int lane = threadIdx.x & 63;
+    const int w0 = (int)(threadIdx.x & ~63u);
+    if (threadIdx.x == 0) sfac[n_sp] = 0.0f;  // the factor of the padding entries
+    for (int j0 = __builtin_amdgcn_readfirstlane(w0); j0 < n_sp; j0 += BATCH * block) {
+        uint32_t r[BATCH];
+        float g[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {  // lanes past the end re-read the last record
+            const int j = min(j0 + u * block + lane, n_sp - 1);
+            r[u] = rec[j];
+            if (ACT) g[u] = sf[rgrp[j]];
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
-            const float4 xj = sx[q[u] & 0xFFFFu];
-            const float2 c = st[q[u] >> 16];
-            const float l0 = ACT ? c.y * f[u] : c.y;
-            hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
+            const int j = j0 + u * block + lane;
+            const float4 xa = lds_f4((r[u] << 4) & (((1u << kRecA) - 1u) << 4));
+            const float4 xb = lds_f4((r[u] >> (kRecA - 4)) & (((1u << kRecB) - 1u) << 4));
+            const float4 c = lds_f4(((r[u] >> (kRecA + kRecB)) << 4) | tbase);
+            bool plain = !EXACT;
+            if (EXACT) {
+                const float m = fminf(fminf(fabsf(xa.x), fabsf(xa.y)), fabsf(xa.z));
+                plain = __builtin_amdgcn_ballot_w64(j < n_sp && !(m >= safe)) == 0;
+            }
+            float dx, dy, dz, fac;
+            if (plain) fac = hooke_fac_tab<ACT, kPlain>(xa, xb, c, ACT ? g[u] : 1.0f, dx, dy, dz);
+            else fac = hooke_fac_tab<ACT, kExactAll>(xa, xb, c, ACT ? g[u] : 1.0f, dx, dy, dz);
+            if (j < n_sp) sfac[j] = fac;
         }
     }
-    for (; r < w; ++r) {
-        const uint32_t q = pp[r * 64];
-        const float2 c = st[q >> 16];
-        const float l0 = ACT ? c.y * factor[pg[r * 64]] : c.y;
-        const float4 xj = sx[q & 0xFFFFu];
-        hooke<EXACT>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, l0, fx, fy, fz);
+}
+
+// Gather pass: each lane walks its mass's entries in the usual order; an entry holds the
+// neighbour's LDS slot (bits 0-12) and the index of the spring's factor in sfac (bits 13-31).
+// Its arithmetic is light, so the entry loads would sit exposed: the first kPre entries of
+// the slice are loaded (`prefetch_entries`) before the spring pass and consumed after it.
+constexpr int kPre = 16;
+
+struct SliceEntries {
+    const uint32_t* pp;  // this lane's first entry
+    int w;               // entries per lane (uniform over the wavefront)
+    uint32_t pre[kPre];
+};
+
+__device__ __forceinline__ void prefetch_entries(SliceEntries& se, int s, int nslice,
+                                                 const int32_t* __restrict__ slice_ptr,
+                                                 const uint32_t* __restrict__ packed) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    se.w = 0;
+    se.pp = packed;
+    if (s >= nslice) return;
+    const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
+    se.w = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
+    se.pp = packed + e0 + (threadIdx.x & 63);
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+        if (u < se.w) se.pre[u] = se.pp[u * 64];
+}
+
+template <int BATCH>
+__device__ __forceinline__ void gather_split(uint32_t fbase, float4 xi, const SliceEntries& se, float& fx, float& fy,
+                                             float& fz) {
+    fx = fy = fz = 0.0f;
+    auto one = [&](uint32_t q) {
+        const float4 xj = lds_f4((q & ((1u << kSlotBits) - 1u)) << 4);
+        const float fac = lds_f1(((q >> kSlotBits) << 2) + fbase);
+        fx = __builtin_fmaf(fac, xj.x - xi.x, fx);
+        fy = __builtin_fmaf(fac, xj.y - xi.y, fy);
+        fz = __builtin_fmaf(fac, xj.z - xi.z, fz);
+    };
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+        if (u < se.w) one(se.pre[u]);
+    int r = kPre;
+    for (; r + BATCH <= se.w; r += BATCH) {
+        uint32_t q[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) q[u] = se.pp[(r + u) * 64];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) one(q[u]);
     }
+    for (; r < se.w; ++r) one(se.pp[r * 64]);
 }
 
 struct StepArgs {
@@ -209,37 +371,77 @@ struct StepArgs {
     const float* __restrict__ factor;
     const float* __restrict__ fext;
     float* __restrict__ vstar_out;   // optional: velocity before friction and damping (adjoint recompute)
-    const uint32_t* __restrict__ packed;   // compact entries (slot | table index << 16), or null
-    const float2* __restrict__ table;      // (k, L0) pairs of the compact entries
-    int n, nblk, nslice, block, n_table, lds_slots;
+    const uint32_t* __restrict__ packed;   // compact entries (see gather_table), or null
+    const float4* __restrict__ table;      // (k, L0, L0^2, residual) of the compact entries
+    const int2* __restrict__ blk_groups;   // per workgroup: first factor index and count
+    const uint32_t* __restrict__ sp_rec;   // split form: spring records, workgroup after workgroup
+    const uint16_t* __restrict__ sp_grp;   // split form: local actuation factor index per record
+    const int32_t* __restrict__ sp_ptr;    // split form: first record of each workgroup
+    int n, nblk, nslice, block, n_table, lds_slots, max_local_groups;
 };
+
+// Difference mode of a wavefront (uniform across it).  A coordinate at least `safe` away from
+// zero makes its difference with any neighbour closer than safe/2 exact (Sterbenz), and a
+// spring longer than that is far from rest, where a one-ulp error in d is negligible; so an
+// axis needs the residual terms only if some mass of the wavefront is nearer its plane.
+__device__ __forceinline__ int difference_mode(float4 xi, float safe) {
+    const bool nx = __builtin_amdgcn_ballot_w64(!(fabsf(xi.x) >= safe)) != 0;
+    const bool ny = __builtin_amdgcn_ballot_w64(!(fabsf(xi.y) >= safe)) != 0;
+    const bool nz = __builtin_amdgcn_ballot_w64(!(fabsf(xi.z) >= safe)) != 0;
+    return (nx || ny) ? kExactAll : nz ? kExactZ : kPlain;
+}
+
+// The exact-difference loop holds more live values per entry; it loads half as far ahead so
+// that it does not raise the kernel's register count (and cut its occupancy).
+template <int BATCH>
+constexpr int kExactBatch = BATCH > 2 ? BATCH / 2 : BATCH;
+
+// Step modes: explicit (k, L0) per entry, compact entries with the parameter table, split.
+enum : int { kExplicit = 0, kTable = 1, kSplit = 2 };
 
 // One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
 // damping, symplectic Euler, fixed masses.
-template <bool ACT, bool EXACT, int BATCH, bool TABLE>
+template <bool ACT, bool EXACT, int BATCH, int MODE>
 __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b) {
+    constexpr bool TABLE = MODE != kExplicit;
     const int base = b * a.block;
-    float2* st = reinterpret_cast<float2*>(sx + a.lds_slots);
-    if (TABLE)
+    const uint32_t tbase = table_base(a.lds_slots);
+    float4* st = reinterpret_cast<float4*>(reinterpret_cast<char*>(sx) + tbase);
+    float* sf = reinterpret_cast<float*>(st + a.n_table);
+    float* sfac = sf + a.max_local_groups + 1;
+    if (TABLE) {
         for (int q = threadIdx.x; q < a.n_table; q += a.block) st[q] = a.table[q];
+        if (ACT) {
+            const int2 bg = a.blk_groups[b];
+            for (int q = threadIdx.x; q <= bg.y; q += a.block) sf[q] = q ? a.factor[bg.x + q - 1] : 1.0f;
+        }
+    }
     const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
     const float4 xi = sx[own];
     float fx, fy, fz;
-    // Coordinates at least `safe` away from zero make every difference with a neighbour closer
-    // than safe/2 exact (Sterbenz), and a spring longer than that is far from rest, where a
-    // one-ulp error in d is negligible; such wavefronts skip the residual terms.
-    bool plain = !EXACT;
-    if (EXACT) {
-        const float m = fminf(fminf(fabsf(xi.x), fabsf(xi.y)), fabsf(xi.z));
-        plain = __builtin_amdgcn_ballot_w64(!(m >= p.safe)) == 0;
-    }
     const int s = (base + (int)threadIdx.x) >> 6;
-    if (TABLE) {
-        if (plain) gather_table<ACT, false, BATCH>(sx, st, xi, s, a.nslice, a.slice_ptr, a.packed, a.grp, a.factor, fx, fy, fz);
-        else gather_table<ACT, true, BATCH>(sx, st, xi, s, a.nslice, a.slice_ptr, a.packed, a.grp, a.factor, fx, fy, fz);
+    if (MODE == kSplit) {
+        SliceEntries se;
+        prefetch_entries(se, s, a.nslice, a.slice_ptr, a.packed);
+        const int r0 = a.sp_ptr[b];
+        spring_pass<ACT, EXACT, BATCH>(sx, tbase, sf, sfac, a.sp_rec + r0, ACT ? a.sp_grp + r0 : nullptr,
+                                       a.sp_ptr[b + 1] - r0, a.block, p.safe);
+        __syncthreads();
+        gather_split<BATCH>(tbase + (uint32_t)(reinterpret_cast<char*>(sfac) - reinterpret_cast<char*>(st)), xi, se,
+                            fx, fy, fz);
     } else {
-        if (plain) gather<ACT, false, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
-        else gather<ACT, true, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+        const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
+        if (TABLE) {
+            if (mode == kPlain) gather_table<ACT, kPlain, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+            else if (mode == kExactZ)
+                gather_table<ACT, kExactZ, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+            else gather_table<ACT, kExactAll, kExactBatch<BATCH>>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+        } else {
+            if (mode == kPlain) gather<ACT, kPlain, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+            else if (mode == kExactZ)
+                gather<ACT, kExactZ, BATCH>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+            else gather<ACT, kExactAll, kExactBatch<BATCH>>(sx, xi, s, a.nslice, a.slice_ptr, a.nbr, a.kl, a.grp, a.factor, fx, fy, fz);
+        }
     }
     const int i = base + own;
     if (i >= a.n) return;
@@ -295,17 +497,17 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
 }
 
 // One workgroup per block.
-template <bool ACT, bool EXACT, int BATCH, bool TABLE>
+template <bool ACT, bool EXACT, int BATCH, int MODE>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     const int b = logical_block(a.nblk);
     if (b >= a.nblk) return;
-    step_block<ACT, EXACT, BATCH, TABLE>(sx, a, p, b);
+    step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b);
 }
 
 // Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
 // on XCD w % 8 and takes that XCD's contiguous eighth of the blocks in strides.
-template <bool ACT, bool EXACT, int BATCH, bool TABLE>
+template <bool ACT, bool EXACT, int BATCH, int MODE>
 __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     const int per = (a.nblk + 7) >> 3;
@@ -314,7 +516,7 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
     for (int j = (int)(blockIdx.x >> 3); j < per; j += stride) {
         const int b = xcd * per + j;
         if (b >= a.nblk) break;
-        step_block<ACT, EXACT, BATCH, TABLE>(sx, a, p, b);
+        step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b);
         __syncthreads();  // LDS is restaged for the next block
     }
 }
@@ -336,11 +538,11 @@ forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, co
     const float4 xi = sx[own];
     float fx, fy, fz;
     // the same choice of difference as the step, so this is the force the step integrates
-    const float mc = fminf(fminf(fabsf(xi.x), fabsf(xi.y)), fabsf(xi.z));
-    const bool plain = !p.exact || __builtin_amdgcn_ballot_w64(!(mc >= p.safe)) == 0;
+    const int mode = p.exact ? difference_mode(xi, p.safe) : kPlain;
     const int s = (base + (int)threadIdx.x) >> 6;
-    if (plain) gather<ACT, false, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
-    else gather<ACT, true, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    if (mode == kPlain) gather<ACT, kPlain, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    else if (mode == kExactZ) gather<ACT, kExactZ, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
+    else gather<ACT, kExactAll, 4>(sx, xi, s, nslice, slice_ptr, nbr, kl, grp, factor, fx, fy, fz);
     const int i = base + own;
     if (i >= n) return;
     const float m = mass[i];
@@ -361,21 +563,32 @@ forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, co
     fout[3 * i + 2] = fz;
 }
 
-// Actuation table at t_n = n dt for the device step counter n: factor[g] = 1 + A_g sin(w t_n
-// + phi_g) evaluated in FP64 and rounded once to FP32; factor[n_factor] = 1 (passive springs).
-// With `advance`, the counter moves to n + 1 (the step that follows consumes the table).
-// Launched as ONE workgroup, so the counter update cannot race with its reads.
-__global__ void __launch_bounds__(1024)
-actuation_kernel(const double* __restrict__ phase, const double* __restrict__ amp, double omega, double dt,
-                 long long* __restrict__ step_ctr, float* __restrict__ factor, int n_factor, int advance,
-                 long long n_explicit) {
+// Actuation factors 1 + A_g sin(2 pi f t_n + phi_g) of eq. (2)'s rest lengths at step n, one per
+// (body, group), FP32.  The elapsed fraction of a period, frac(n f dt), is formed exactly in
+// 64-bit fixed point (n * cycles wraps modulo 2^64), so the phase stays accurate to ~1e-7 rad
+// however many steps have been taken.  With `advance`, the last workgroup to finish moves the
+// device step counter on (every workgroup has read it by then).
+__global__ void __launch_bounds__(256)
+actuation_kernel(const float* __restrict__ phase, const float* __restrict__ amp, unsigned long long cycles,
+                 long long* __restrict__ step_ctr, unsigned* __restrict__ done, float* __restrict__ factor,
+                 int n_factor, int advance, long long n_explicit) {
     const long long n = n_explicit >= 0 ? n_explicit : *step_ctr;
-    const double t = (double)n * dt;
-    for (int g = threadIdx.x; g < n_factor; g += blockDim.x)
-        factor[g] = (float)(1.0 + amp[g] * sin(omega * t + phase[g]));
-    if (threadIdx.x == 0) factor[n_factor] = 1.0f;
-    __syncthreads();
-    if (advance && threadIdx.x == 0) *step_ctr = n + 1;
+    const unsigned long long frac = (unsigned long long)n * cycles;
+    const float u = (float)(unsigned)(frac >> 32) * 0x1p-32f;
+    const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (g < n_factor) factor[g] = __builtin_fmaf(amp[g], sinf(__builtin_fmaf(6.28318531f, u, phase[g])), 1.0f);
+    else if (g == n_factor) factor[g] = 1.0f;
+    if (advance) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicAdd(done, 1u) == gridDim.x - 1) {
+                *step_ctr = n + 1;
+                *done = 0u;
+                __threadfence();
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- FP64 diagnostics
@@ -649,33 +862,58 @@ hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipS
     return launch_step_io(d, d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], nullptr, p, st);
 }
 
+// Dynamic LDS of one step workgroup: positions, then (table and split modes) the parameter
+// table and the workgroup's actuation factors, then (split mode) the spring factors.
+hipError_t step_static_lds(size_t* bytes) {
+    const void* ks[] = {(const void*)step_kernel<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kTable>,
+                        (const void*)step_persistent<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kSplit>,
+                        (const void*)step_persistent<true, false, 8, kSplit>};
+    *bytes = 0;
+    for (const void* k : ks) {
+        hipFuncAttributes at{};
+        hipError_t e = hipFuncGetAttributes(&at, k);
+        if (e != hipSuccess) return e;
+        *bytes = std::max(*bytes, (size_t)at.sharedSizeBytes);
+    }
+    return hipSuccess;
+}
+
+size_t step_lds_bytes(const DeviceArrays& d) {
+    size_t b = (size_t)d.lds_slots * sizeof(float4);
+    if (d.packed)
+        b = table_base(d.lds_slots) + (size_t)d.n_table * sizeof(float4) + (size_t)(d.max_local_groups + 1) * sizeof(float);
+    if (d.sp_rec) b += (size_t)(d.max_sp + 1) * sizeof(float);
+    return b;
+}
+
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
                           float* vstar, const StepParams& p, hipStream_t st) {
-    const bool table = d.packed != nullptr;
+    const int mode = d.sp_rec ? kSplit : d.packed ? kTable : kExplicit;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
-               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.table, (int)d.n, (int)d.nblk, (int)d.nslice, d.block,
-               d.n_table, d.lds_slots};
-    const size_t lds = (size_t)d.lds_slots * sizeof(float4) + (table ? (size_t)d.n_table * sizeof(float2) : 0);
+               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr,
+               (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups};
+    const size_t lds = step_lds_bytes(d);
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
     auto go = [&](auto normal, auto pers) {
         if (persistent) hipLaunchKernelGGL(pers, grid, dim3(d.block), lds, st, a, p);
         else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds, st, a, p);
     };
-#define CRONOS_GO(A, E, B, T) go(step_kernel<A, E, B, T>, step_persistent<A, E, B, T>)
-#define CRONOS_GO_T(A, E, B) (table ? CRONOS_GO(A, E, B, true) : CRONOS_GO(A, E, B, false))
+#define CRONOS_GO(A, E, B, M) go(step_kernel<A, E, B, M>, step_persistent<A, E, B, M>)
+#define CRONOS_GO_M(A, E, B) \
+    (mode == kSplit ? CRONOS_GO(A, E, B, kSplit) : mode == kTable ? CRONOS_GO(A, E, B, kTable) : CRONOS_GO(A, E, B, kExplicit))
     const bool act = d.grp != nullptr, ex = p.exact != 0;
     if (d.batch == 8) {
-        if (act) ex ? CRONOS_GO_T(true, true, 8) : CRONOS_GO_T(true, false, 8);
-        else ex ? CRONOS_GO_T(false, true, 8) : CRONOS_GO_T(false, false, 8);
+        if (act) ex ? CRONOS_GO_M(true, true, 8) : CRONOS_GO_M(true, false, 8);
+        else ex ? CRONOS_GO_M(false, true, 8) : CRONOS_GO_M(false, false, 8);
     } else if (d.batch == 2) {
-        if (act) ex ? CRONOS_GO_T(true, true, 2) : CRONOS_GO_T(true, false, 2);
-        else ex ? CRONOS_GO_T(false, true, 2) : CRONOS_GO_T(false, false, 2);
+        if (act) ex ? CRONOS_GO_M(true, true, 2) : CRONOS_GO_M(true, false, 2);
+        else ex ? CRONOS_GO_M(false, true, 2) : CRONOS_GO_M(false, false, 2);
     } else {
-        if (act) ex ? CRONOS_GO_T(true, true, 4) : CRONOS_GO_T(true, false, 4);
-        else ex ? CRONOS_GO_T(false, true, 4) : CRONOS_GO_T(false, false, 4);
+        if (act) ex ? CRONOS_GO_M(true, true, 4) : CRONOS_GO_M(true, false, 4);
+        else ex ? CRONOS_GO_M(false, true, 4) : CRONOS_GO_M(false, false, 4);
     }
-#undef CRONOS_GO_T
+#undef CRONOS_GO_M
 #undef CRONOS_GO
     return hipGetLastError();
 }
@@ -685,11 +923,14 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const bool table = d.packed != nullptr;
-    const size_t lds = (size_t)d.lds_slots * sizeof(float4) + (table ? (size_t)d.n_table * sizeof(float2) : 0);
-    const void* k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4, true> : (const void*)step_persistent<true, false, 4, true>)
-                          : (exact ? (const void*)step_persistent<false, true, 4, true> : (const void*)step_persistent<false, false, 4, true>);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, lds);
+    const void* k;
+    if (d.sp_rec)
+        k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4, kSplit> : (const void*)step_persistent<true, false, 4, kSplit>)
+                  : (exact ? (const void*)step_persistent<false, true, 4, kSplit> : (const void*)step_persistent<false, false, 4, kSplit>);
+    else
+        k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4, kTable> : (const void*)step_persistent<true, false, 4, kTable>)
+                  : (exact ? (const void*)step_persistent<false, true, 4, kTable> : (const void*)step_persistent<false, false, 4, kTable>);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, step_lds_bytes(d));
     if (e != hipSuccess) return e;
     int g = std::max(1, per_cu) * cus;
     g = (g + 7) / 8 * 8;
@@ -697,10 +938,11 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
     return hipSuccess;
 }
 
-hipError_t launch_actuation(const DeviceArrays& d, double omega, double dt, int advance, hipStream_t st,
+hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
                             long long n_explicit) {
-    hipLaunchKernelGGL(actuation_kernel, dim3(1), dim3(1024), 0, st, d.phase, d.amp, omega, dt, d.step_ctr, d.factor,
-                       d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
+    const unsigned grid = (unsigned)((d.n_factor + 1 + 255) / 256);
+    hipLaunchKernelGGL(actuation_kernel, dim3(grid), dim3(256), 0, st, d.phase, d.amp, cycles, d.step_ctr, d.act_done,
+                       d.factor, d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
     return hipGetLastError();
 }
 

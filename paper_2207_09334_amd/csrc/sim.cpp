@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -84,6 +85,7 @@ struct cronos_sim_t {
     int64_t step = 0;
     int32_t nb = 1, n_groups = 0;
     double dt = 0.0, omega = 0.0;
+    unsigned long long cycles = 0;       // frac(f dt) * 2^64: period fraction per step
     bool actuated = false, use_graph = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::vector<float> inv_m;            // new order
@@ -102,8 +104,8 @@ namespace {
 
 void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
-    void* ptrs[] = {d.packed, d.table, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
-                    d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
+    void* ptrs[] = {d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
+                    d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.act_done, d.chunks, d.body_chunk, d.chunk_part,
                     d.body_out, d.fout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -142,64 +144,81 @@ double omega_max(const cronos::Layout& L, const cronos_desc& d, const std::vecto
                  const std::vector<double>& mn, const std::vector<uint8_t>& pin, const std::vector<double>& ks,
                  bool& conclusive_gersh, double dt) {
     const int64_t n = L.n, s = L.s;
-    std::vector<double> nx(3 * s);
-    std::vector<double> rowsum(n, 0.0);
-    for (int64_t q = 0; q < s; ++q) {
-        int32_t a = L.ends[2 * q], b = L.ends[2 * q + 1];
-        double dv[3], len2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            dv[c] = xn[3 * b + c] - xn[3 * a + c];
-            len2 += dv[c] * dv[c];
+    std::vector<double> nx(3 * s), gq(s);
+    cronos::parallel_for(s, [&](int64_t q0, int64_t q1) {
+        for (int64_t q = q0; q < q1; ++q) {
+            int32_t a = L.ends[2 * q], b = L.ends[2 * q + 1];
+            double dv[3], len2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                dv[c] = xn[3 * b + c] - xn[3 * a + c];
+                len2 += dv[c] * dv[c];
+            }
+            double len = std::sqrt(len2);
+            double l1 = 0.0, mx = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                nx[3 * q + c] = len > 0 ? dv[c] / len : 0.0;
+                l1 += std::fabs(nx[3 * q + c]);
+                mx = std::max(mx, std::fabs(nx[3 * q + c]));
+            }
+            gq[q] = 2.0 * ks[q] * mx * l1;
         }
-        double len = std::sqrt(len2);
-        double l1 = 0.0, mx = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            nx[3 * q + c] = len > 0 ? dv[c] / len : 0.0;
-            l1 += std::fabs(nx[3 * q + c]);
-            mx = std::max(mx, std::fabs(nx[3 * q + c]));
-        }
-        double g = 2.0 * ks[q] * mx * l1;
-        rowsum[a] += g;
-        rowsum[b] += g;
-    }
+    }, 1 << 16);
+    // row sums over each mass's incidence list (the CSR), then the largest bound
     double kg = d.ground ? d.ground_k : 0.0;
+    std::vector<double> part(64, 0.0);
+    const int64_t per = (n + 63) / 64;
+    cronos::parallel_for(64, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c)
+            for (int64_t i = c * per; i < std::min(n, (c + 1) * per); ++i) {
+                if (pin[i]) continue;
+                double r = 0.0;
+                for (int64_t p = L.row_ptr[i]; p < L.row_ptr[i + 1]; ++p) r += gq[L.sid[p]];
+                part[c] = std::max(part[c], (r + kg) / mn[i]);
+            }
+    }, 1);
     double gersh = 0.0;
-    for (int64_t i = 0; i < n; ++i)
-        if (!pin[i]) gersh = std::max(gersh, (rowsum[i] + kg) / mn[i]);
+    for (double v : part) gersh = std::max(gersh, v);
     conclusive_gersh = std::sqrt(gersh) * dt < 2.0;
     if (conclusive_gersh) return std::sqrt(gersh);
-    // power iteration on B = M^-1/2 K M^-1/2 over free DOFs
-    std::vector<double> u(3 * n), w(3 * n);
+    // power iteration on B = M^-1/2 K M^-1/2 over free DOFs:
+    // (B u)_i = s_i sum_q k_q n_q n_q . (s_i u_i - s_j u_j) + [z] k_g / m_i u_i,  s = m^-1/2,
+    // one mass per task over its incidence list; dot products in 64 fixed chunks
+    std::vector<double> u(3 * n), w(3 * n), sm(n);
+    for (int64_t i = 0; i < n; ++i) sm[i] = 1.0 / std::sqrt(mn[i]);
     for (int64_t i = 0; i < 3 * n; ++i) u[i] = pin[i / 3] ? 0.0 : 1.0 + 0.37 * std::sin(0.91 * (double)i);
+    auto chunked = [&](auto body) {
+        std::vector<double> acc(64, 0.0);
+        cronos::parallel_for(64, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c)
+                for (int64_t i = c * per; i < std::min(n, (c + 1) * per); ++i) acc[c] += body(i);
+        }, 1);
+        double t = 0.0;
+        for (double v : acc) t += v;
+        return t;
+    };
     double lam = 0.0;
     for (int it = 0; it < 400; ++it) {
-        double nrm = 0.0;
-        for (double v : u) nrm += v * v;
-        nrm = std::sqrt(nrm);
+        double nrm = std::sqrt(chunked([&](int64_t i) {
+            return u[3 * i] * u[3 * i] + u[3 * i + 1] * u[3 * i + 1] + u[3 * i + 2] * u[3 * i + 2];
+        }));
         if (nrm == 0.0) break;
         for (double& v : u) v /= nrm;
-        std::fill(w.begin(), w.end(), 0.0);
-        for (int64_t q = 0; q < s; ++q) {
-            int32_t a = L.ends[2 * q], b = L.ends[2 * q + 1];
-            double sa = 1.0 / std::sqrt(mn[a]), sb = 1.0 / std::sqrt(mn[b]);
-            double proj = 0.0;
-            for (int c = 0; c < 3; ++c) proj += nx[3 * q + c] * (u[3 * b + c] * sb - u[3 * a + c] * sa);
-            for (int c = 0; c < 3; ++c) {
-                double f = ks[q] * proj * nx[3 * q + c];
-                w[3 * a + c] -= f * sa;
-                w[3 * b + c] += f * sb;
+        const double lam_new = chunked([&](int64_t i) {
+            double wi[3] = {0.0, 0.0, 0.0};
+            if (!pin[i]) {
+                for (int64_t p = L.row_ptr[i]; p < L.row_ptr[i + 1]; ++p) {
+                    const int64_t q = L.sid[p], j = L.col[p];
+                    const double* nq = &nx[3 * q];
+                    double proj = 0.0;
+                    for (int c = 0; c < 3; ++c) proj += nq[c] * (sm[i] * u[3 * i + c] - sm[j] * u[3 * j + c]);
+                    for (int c = 0; c < 3; ++c) wi[c] += ks[q] * proj * nq[c];
+                }
+                for (int c = 0; c < 3; ++c) wi[c] *= sm[i];
+                wi[2] += kg / mn[i] * u[3 * i + 2];
             }
-        }
-        for (int64_t i = 0; i < n; ++i) {
-            if (pin[i]) {
-                w[3 * i] = w[3 * i + 1] = w[3 * i + 2] = 0.0;
-                continue;
-            }
-            w[3 * i + 2] += kg / mn[i] * u[3 * i + 2];
-        }
-        // Rayleigh quotient of the unit vector u: w = B u
-        double lam_new = 0.0;
-        for (int64_t i = 0; i < 3 * n; ++i) lam_new += u[i] * w[i];
+            for (int c = 0; c < 3; ++c) w[3 * i + c] = wi[c];
+            return u[3 * i] * wi[0] + u[3 * i + 1] * wi[1] + u[3 * i + 2] * wi[2];  // Rayleigh quotient
+        });
         if (it > 20 && std::fabs(lam_new - lam) <= 1e-7 * std::fabs(lam_new)) {
             lam = lam_new;
             break;
@@ -212,7 +231,7 @@ double omega_max(const cronos::Layout& L, const cronos_desc& d, const std::vecto
 
 cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
     for (int64_t k = 0; k < n; ++k) {
-        if (s->actuated) HIP_TRY(cronos::launch_actuation(s->d, s->omega, s->dt, 1, s->stream));
+        if (s->actuated) HIP_TRY(cronos::launch_actuation(s->d, s->cycles, 1, s->stream));
         HIP_TRY(cronos::launch_step(s->d, s->cur, s->p, s->stream));
         s->cur ^= 1;
     }
@@ -391,12 +410,11 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         }
     }
 
-    // Device coordinates: without a contact plane, shifted so every mass starts at least
-    // `delta` (a power of two of at least twice the fast-path threshold) above zero on each
-    // axis, which lets nearly every wavefront take plain differences.  With the contact plane
-    // the user's frame is kept (the plane at device z = ground_z): penetrations of micrometres
-    // and stick/slip at the feet need the fine resolution FP32 has near the origin, and the
-    // shift would coarsen it; wavefronts near a coordinate plane take exact differences.
+    // Device coordinates: shifted so every mass starts at least `delta` (a power of two of at
+    // least twice the fast-path threshold) above zero on each axis, which lets nearly every
+    // wavefront take plain differences.  With the contact plane z is not shifted (the plane
+    // stays at device z = ground_z): penetrations of micrometres need the fine resolution FP32
+    // has near zero; wavefronts near z = 0 take exact differences in z.
     {
         double rest_max = 0.0;
         for (int64_t q = 0; q < s; ++q) rest_max = std::max(rest_max, d->rest[q]);
@@ -407,7 +425,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         for (int c = 0; c < 3; ++c) {
             double lo = xn[c];
             for (int64_t i = 0; i < n; ++i) lo = std::min(lo, xn[3 * i + c]);
-            sim->origin[c] = (d->ground || (d->flags & CRONOS_NO_SHIFT)) ? 0.0 : lo - delta;
+            sim->origin[c] = ((d->ground && c == 2) || (d->flags & CRONOS_NO_SHIFT)) ? 0.0 : lo - delta;
         }
     }
     std::vector<float4> hx(n);
@@ -444,49 +462,198 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             spring_body[q] = b;
         }
     }
-    for (int64_t e = 0; e < entries; ++e) {
-        int32_t pos = L.entry_csr[e];
-        if (pos < 0) {
-            hkl[e] = make_float2(0.0f, 0.0f);
-            continue;
+    cronos::parallel_for(entries, [&](int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e) {
+            int32_t pos = L.entry_csr[e];
+            if (pos < 0) {
+                hkl[e] = make_float2(0.0f, 0.0f);
+                continue;
+            }
+            int32_t sn = L.sid[pos], si = L.spring_perm[sn];
+            hkl[e] = make_float2((float)d->k[si], (float)d->rest[si]);
+            if (sim->actuated && d->group[si] >= 0) hg[e] = (uint16_t)(spring_body[sn] * sim->n_groups + d->group[si]);
         }
-        int32_t sn = L.sid[pos], si = L.spring_perm[sn];
-        hkl[e] = make_float2((float)d->k[si], (float)d->rest[si]);
-        if (sim->actuated && d->group[si] >= 0) hg[e] = (uint16_t)(spring_body[sn] * sim->n_groups + d->group[si]);
-    }
+    }, 1 << 16);
 
     // compact entry stream: the distinct (k, L0) pairs (in order of first use) and one 32-bit
-    // word per entry, slot | pair index << 16; skipped when there are too many pairs
-    constexpr int kMaxTable = 1024;
+    // word per entry.  Actuated: LDS slot (13 bits) | pair index (9 bits) | 1 + the spring's
+    // actuation factor index relative to the first one its workgroup uses (10 bits; 0 =
+    // passive).  Passive: slot << 19 | pair index << 4 (byte offsets for the kernel).  Not used
+    // when a field would overflow; the explicit per-entry stream then serves.
+    constexpr int kSlotBits = 13, kTypeBits = 9, kGroupBits = 10;
     std::vector<float2> htable;
     std::vector<uint32_t> hpacked;
-    if (!(d->flags & CRONOS_NO_TABLE)) {
-        std::unordered_map<uint64_t, uint32_t> index;
-        hpacked.resize(entries);
-        bool ok = true;
-        for (int64_t e = 0; e < entries && ok; ++e) {
+    std::vector<int2> hblk_groups;
+    int32_t max_local_groups = 0;
+    if (!(d->flags & CRONOS_NO_TABLE) && (L.block + L.max_halo) <= (1 << kSlotBits)) {
+        const int64_t spb = L.block / cronos::kSlice;
+        auto key_of = [&](int64_t e) {
             uint32_t kb, lb;
             std::memcpy(&kb, &hkl[e].x, 4);
             std::memcpy(&lb, &hkl[e].y, 4);
-            const uint64_t key = ((uint64_t)kb << 32) | lb;
-            auto it = index.find(key);
-            uint32_t id;
-            if (it == index.end()) {
-                if ((int)htable.size() >= kMaxTable) {
-                    ok = false;
-                    break;
+            return ((uint64_t)kb << 32) | lb;
+        };
+        // distinct pairs of each workgroup in order of first use, then numbered in workgroup
+        // order: the same numbering as one sequential pass over the entries
+        std::vector<std::vector<uint64_t>> firsts(L.nblk);
+        std::atomic<bool> ok{true};
+        if (sim->actuated) hblk_groups.assign(L.nblk, make_int2(0, 0));
+        cronos::parallel_for(L.nblk, [&](int64_t b0, int64_t b1) {
+            std::unordered_map<uint64_t, char> seen;
+            for (int64_t b = b0; b < b1; ++b) {
+                seen.clear();
+                int lo = 1 << 30, hi = -1;
+                for (int64_t e = L.slice_ptr[b * spb]; e < L.slice_ptr[(b + 1) * spb]; ++e) {
+                    const uint64_t key = key_of(e);
+                    if (seen.emplace(key, 0).second) firsts[b].push_back(key);
+                    if (sim->actuated && hg[e] < n_factor) {
+                        lo = std::min<int>(lo, hg[e]);
+                        hi = std::max<int>(hi, hg[e]);
+                    }
                 }
-                id = (uint32_t)htable.size();
-                index.emplace(key, id);
-                htable.push_back(hkl[e]);
-            } else {
-                id = it->second;
+                if (hi >= 0) {
+                    hblk_groups[b] = make_int2(lo, hi - lo + 1);
+                    if (hi - lo + 1 >= (1 << kGroupBits)) ok = false;
+                }
             }
-            hpacked[e] = (uint32_t)L.nbr_local[e] | (id << 16);
+        }, 16);
+        std::unordered_map<uint64_t, uint32_t> index;
+        for (int64_t b = 0; b < L.nblk && ok; ++b) {
+            for (uint64_t key : firsts[b])
+                if (index.find(key) == index.end()) {
+                    if ((int)htable.size() >= (1 << kTypeBits)) {
+                        ok = false;
+                        break;
+                    }
+                    index.emplace(key, (uint32_t)htable.size());
+                    float2 c;
+                    const uint32_t kb = (uint32_t)(key >> 32), lb = (uint32_t)key;
+                    std::memcpy(&c.x, &kb, 4);
+                    std::memcpy(&c.y, &lb, 4);
+                    htable.push_back(c);
+                }
+            if (sim->actuated) max_local_groups = std::max(max_local_groups, hblk_groups[b].y);
         }
-        if (!ok) {
+        if (ok) {
+            hpacked.resize(entries);
+            cronos::parallel_for(L.nblk, [&](int64_t b0, int64_t b1) {
+                for (int64_t b = b0; b < b1; ++b)
+                    for (int64_t e = L.slice_ptr[b * spb]; e < L.slice_ptr[(b + 1) * spb]; ++e) {
+                        const uint32_t id = index.find(key_of(e))->second;
+                        uint32_t lg = 0;
+                        if (sim->actuated && hg[e] < n_factor) lg = (uint32_t)(hg[e] - hblk_groups[b].x + 1);
+                        hpacked[e] = sim->actuated ? (uint32_t)L.nbr_local[e] | (id << kSlotBits) | (lg << (kSlotBits + kTypeBits))
+                                                   : ((uint32_t)L.nbr_local[e] << 19) | (id << 4);
+                    }
+            }, 16);
+        } else {
             htable.clear();
-            hpacked.clear();
+            hblk_groups.clear();
+            max_local_groups = 0;
+        }
+    }
+
+    // split form: per workgroup, one record per spring with an end among its masses (in mass
+    // order, then incidence order; a spring between two of its masses is recorded by the end
+    // with the lower slot) and, per entry, the neighbour slot | record index << 13; padding
+    // entries point at the record count, whose factor the kernel sets to zero.  Needs the
+    // compact form, first-end slots below 1024 and the factors within LDS.
+    std::vector<uint32_t> hsplit, hsp_rec;
+    std::vector<uint16_t> hsp_grp;
+    std::vector<int32_t> hsp_ptr;
+    int32_t max_sp = 0;
+    if (!htable.empty() && (d->flags & CRONOS_SPLIT) && L.block <= 1024) {
+        const int64_t spb = L.block / cronos::kSlice;
+        auto type_of = [&](int64_t e) -> uint32_t {
+            return sim->actuated ? (hpacked[e] >> kSlotBits) & ((1u << kTypeBits) - 1u) : (hpacked[e] >> 4) & ((1u << kTypeBits) - 1u);
+        };
+        std::vector<std::vector<uint32_t>> rec(L.nblk);
+        std::vector<std::vector<uint16_t>> rgrp(sim->actuated ? L.nblk : 0);
+        hsplit.resize(entries);
+        std::atomic<bool> ok{true}, consistent{true};
+        cronos::parallel_for(L.nblk, [&](int64_t b0, int64_t b1) {
+            std::vector<int32_t> lane_of(L.block);
+            std::unordered_map<int32_t, uint32_t> first;
+            for (int64_t b = b0; b < b1; ++b) {
+                const int64_t base = b * L.block;
+                for (int l = 0; l < L.block; ++l) lane_of[L.lane_mass[base + l]] = l;
+                first.clear();
+                std::vector<uint32_t>& R = rec[b];
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int m = 0; m < L.block; ++m) {
+                        const int64_t i = base + m;
+                        const int l = lane_of[m];
+                        const int64_t sl = (base + l) / cronos::kSlice;
+                        const int64_t w = (L.slice_ptr[sl + 1] - L.slice_ptr[sl]) / cronos::kSlice;
+                        const int64_t deg = i < n ? L.row_ptr[i + 1] - L.row_ptr[i] : 0;
+                        for (int64_t r = 0; r < w; ++r) {
+                            const int64_t e = L.slice_ptr[sl] + r * cronos::kSlice + (l % cronos::kSlice);
+                            const uint32_t slot = L.nbr_local[e];
+                            if (r >= deg) continue;  // padding, resolved once the count is known
+                            const int32_t sn = L.sid[L.entry_csr[e]];
+                            const bool producer = slot >= (uint32_t)L.block || (uint32_t)m < slot;
+                            if (pass == 0 && producer) {
+                                const uint32_t type = type_of(e);
+                                first.emplace(sn, (uint32_t)R.size());
+                                R.push_back((uint32_t)m | (slot << 10) | (type << 23));
+                                if (sim->actuated) rgrp[b].push_back((uint16_t)(hpacked[e] >> (kSlotBits + kTypeBits)));  // local factor
+                            } else if (pass == 1) {
+                                auto it = first.find(sn);
+                                if (it == first.end()) {
+                                    consistent = false;
+                                    continue;
+                                }
+                                hsplit[e] = slot | (it->second << kSlotBits);
+                            }
+                        }
+                    }
+                if (R.size() >= (size_t(1) << (32 - kSlotBits))) ok = false;
+                // padding entries: record count (zero factor); then every entry is checked
+                // against its record: same two ends, parameter pair and actuation factor
+                const uint32_t n_sp = (uint32_t)R.size();
+                for (int64_t sl = base / cronos::kSlice; sl < base / cronos::kSlice + spb; ++sl)
+                    for (int64_t e = L.slice_ptr[sl]; e < L.slice_ptr[sl + 1]; ++e) {
+                        const uint32_t own = L.lane_mass[sl * cronos::kSlice + (e - L.slice_ptr[sl]) % cronos::kSlice];
+                        const uint32_t slot = L.nbr_local[e];
+                        if (L.entry_csr[e] < 0) {
+                            hsplit[e] = slot | (n_sp << kSlotBits);
+                            continue;
+                        }
+                        const uint32_t j = hsplit[e] >> kSlotBits;
+                        if ((hsplit[e] & ((1u << kSlotBits) - 1u)) != slot || j >= n_sp) {
+                            consistent = false;
+                            continue;
+                        }
+                        const uint32_t ra = R[j] & 1023u, rb = (R[j] >> 10) & 8191u, rt = R[j] >> 23;
+                        const bool ends = (ra == own && rb == slot) || (ra == slot && rb == own);
+                        const bool type = rt == type_of(e);
+                        const bool grp = !sim->actuated || rgrp[b][j] == (hpacked[e] >> (kSlotBits + kTypeBits));
+                        if (!ends || !type || !grp || rb >= (uint32_t)(L.block + L.max_halo)) consistent = false;
+                    }
+            }
+        }, 16);
+        if (!consistent) {
+            delete sim;
+            return fail(CRONOS_EINVAL, "create: internal error: split incidence form inconsistent");
+        }
+        hsp_ptr.assign(L.nblk + 1, 0);
+        for (int64_t b = 0; b < L.nblk; ++b) {
+            hsp_ptr[b + 1] = hsp_ptr[b] + (int32_t)rec[b].size();
+            max_sp = std::max<int32_t>(max_sp, (int32_t)rec[b].size());
+        }
+        const size_t lds = (size_t)cronos::table_base(L.block + L.max_halo) + htable.size() * sizeof(float4) +
+                           (size_t)(max_local_groups + 1) * sizeof(float) + (size_t)(max_sp + 1) * sizeof(float);
+        if (ok && lds <= 160 * 1024) {
+            hsp_rec.reserve(hsp_ptr[L.nblk]);
+            for (auto& R : rec) hsp_rec.insert(hsp_rec.end(), R.begin(), R.end());
+            if (sim->actuated) {
+                hsp_grp.reserve(hsp_ptr[L.nblk]);
+                for (auto& G : rgrp) hsp_grp.insert(hsp_grp.end(), G.begin(), G.end());
+            }
+        } else {
+            hsplit.clear();
+            hsp_ptr.clear();
+            max_sp = 0;
         }
     }
 
@@ -525,7 +692,14 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         delete sim;
         return fail(CRONOS_EDEVICE, "create: hipSetDevice(%d) failed", d->device);
     }
-    if ((size_t)D.lds_slots * sizeof(float4) + 1024 * sizeof(float2) > 160 * 1024) {
+    {
+        size_t static_lds = 0;
+        if (cronos::step_static_lds(&static_lds) != hipSuccess || static_lds != 0) {
+            delete sim;
+            return fail(CRONOS_EDEVICE, "create: step kernels must not use static LDS (%zu bytes)", static_lds);
+        }
+    }
+    if ((size_t)D.lds_slots * sizeof(float4) > 160 * 1024) {
         delete sim;
         return fail(CRONOS_EINVAL, "create: workgroup halo needs %zu bytes of LDS", (size_t)D.lds_slots * sizeof(float4));
     }
@@ -546,19 +720,35 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         TRY(upload(&D.slice_ptr, L.slice_ptr.data(), L.slice_ptr.size()));
         TRY(upload(&D.nbr, L.nbr_local.data(), entries));
         TRY(upload(&D.kl, hkl.data(), entries));
+        if (!hsp_rec.empty()) {
+            TRY(upload(&D.packed, hsplit.data(), entries));
+            TRY(upload(&D.sp_rec, hsp_rec.data(), hsp_rec.size()));
+            TRY(upload(&D.sp_ptr, hsp_ptr.data(), hsp_ptr.size()));
+            if (sim->actuated) TRY(upload(&D.sp_grp, hsp_grp.data(), hsp_grp.size()));
+            D.max_sp = max_sp;
+        }
         if (!htable.empty()) {
-            TRY(upload(&D.packed, hpacked.data(), entries));
-            TRY(upload(&D.table, htable.data(), htable.size()));
+            if (hsp_rec.empty()) TRY(upload(&D.packed, hpacked.data(), entries));
+            std::vector<float4> tab(htable.size());
+            for (size_t q = 0; q < htable.size(); ++q) {
+                const float l0 = htable[q].y, sq = l0 * l0;
+                tab[q] = make_float4(htable[q].x, l0, sq, std::fmaf(l0, l0, -sq));
+            }
+            TRY(upload(&D.table, tab.data(), tab.size()));
             D.n_table = (int32_t)htable.size();
+            if (sim->actuated) TRY(upload(&D.blk_groups, hblk_groups.data(), hblk_groups.size()));
+            D.max_local_groups = max_local_groups;
         }
         if (sim->actuated) TRY(upload(&D.grp, hg.data(), entries));
         TRY(upload(&D.halo_ptr, L.halo_ptr.data(), L.halo_ptr.size()));
         TRY(upload(&D.halo_idx, L.halo_idx.data(), L.halo_idx.size()));
         std::vector<float> ones(n_factor + 1, 1.0f);
-        std::vector<double> zeros(std::max<int32_t>(n_factor, 1), 0.0);
+        std::vector<float> zeros(std::max<int32_t>(n_factor, 1), 0.0f);
         TRY(upload(&D.factor, ones.data(), ones.size()));
         TRY(upload(&D.phase, zeros.data(), zeros.size()));
         TRY(upload(&D.amp, zeros.data(), zeros.size()));
+        unsigned zero_u = 0;
+        TRY(upload(&D.act_done, &zero_u, 1));
         long long zero = 0;
         TRY(upload(&D.step_ctr, &zero, 1));
         TRY(upload(&D.chunks, chunks.data(), chunks.size()));
@@ -627,9 +817,14 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
         if (!std::isfinite(phase[g]) || !std::isfinite(amp[g])) return fail(CRONOS_EINVAL, "set_actuation: non-finite value");
     HIP_TRY(hipSetDevice(sim->device));
     HIP_TRY(hipStreamSynchronize(sim->stream));
-    HIP_TRY(hipMemcpy(sim->d.phase, phase, m * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(sim->d.amp, amp, m * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> ph(phase, phase + m), am(amp, amp + m);
+    HIP_TRY(hipMemcpy(sim->d.phase, ph.data(), m * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sim->d.amp, am.data(), m * sizeof(float), hipMemcpyHostToDevice));
     sim->omega = 2.0 * M_PI * freq_hz;
+    {
+        const double c = freq_hz * sim->dt;
+        sim->cycles = (unsigned long long)std::ldexp(c - std::floor(c), 64);
+    }
     double amax = 0.0;
     for (size_t g = 0; g < m; ++g) amax = std::max(amax, std::fabs(amp[g]));
     sim->p.safe = (float)(4.0 * sim->rest_max * (1.0 + amax));
@@ -724,7 +919,7 @@ extern "C" cronos_status cronos_eval_forces(cronos_sim sim, double* f) {
     if (!sim || !f) return fail(CRONOS_EINVAL, "eval_forces: NULL argument");
     const int64_t n = sim->d.n;
     HIP_TRY(hipSetDevice(sim->device));
-    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->omega, sim->dt, 0, sim->stream));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
     HIP_TRY(cronos::launch_forces(sim->d, sim->cur, sim->p, sim->stream));
     if (!sim->h_f) HIP_TRY(hipHostMalloc((void**)&sim->h_f, 3 * n * sizeof(float), 0));
     HIP_TRY(hipMemcpyAsync(sim->h_f, sim->d.fout, 3 * n * sizeof(float), hipMemcpyDeviceToHost, sim->stream));
@@ -741,7 +936,7 @@ extern "C" cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out) {
     if (!sim || !out) return fail(CRONOS_EINVAL, "diagnostics: NULL argument");
     HIP_TRY(hipSetDevice(sim->device));
     const int nb = sim->nb;
-    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->omega, sim->dt, 0, sim->stream));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
     HIP_TRY(cronos::launch_diagnostics(sim->d, sim->cur, sim->p, sim->stream));
     if (!sim->h_diag) HIP_TRY(hipHostMalloc((void**)&sim->h_diag, (size_t)nb * cronos::kDiagFields * sizeof(double), 0));
     HIP_TRY(hipMemcpyAsync(sim->h_diag, sim->d.body_out, (size_t)nb * cronos::kDiagFields * sizeof(double),
@@ -876,14 +1071,14 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
         HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
         for (int32_t k = 0; k < steps; ++k) {
-            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->omega, sim->dt, 0, st, nc + k));
+            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k));
             HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
                                            R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
                                            R.seg_vs + (size_t)k * 3 * n, sim->p, st));
         }
         for (int32_t k = steps - 1; k >= 0; --k) {
             const double t = (double)(nc + k) * sim->dt;
-            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->omega, sim->dt, 0, st, nc + k));
+            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k));
             HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)k * n, R.seg_vs + (size_t)k * 3 * n, R.xb[cur],
                                              R.vb[cur], R.w, R.vb[cur ^ 1], R.xbl, sim->p, st));
             HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w, R.xbl, R.xb[cur ^ 1], R.sens,
@@ -933,11 +1128,12 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
 }
 
 extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch,
-                                              int32_t* persistent_groups) {
+                                              int32_t* persistent_groups, int32_t* step_form) {
     if (!sim) return fail(CRONOS_EINVAL, "launch_config: NULL handle");
     if (block_masses) *block_masses = sim->lay.block;
     if (batch) *batch = sim->d.batch;
     if (persistent_groups) *persistent_groups = sim->d.persistent_groups;
+    if (step_form) *step_form = sim->d.sp_rec ? CRONOS_FORM_SPLIT : sim->d.packed ? CRONOS_FORM_TABLE : CRONOS_FORM_EXPLICIT;
     return CRONOS_OK;
 }
 

@@ -59,6 +59,9 @@ class Pool:
         ph, am = self.actuation(draw)
         return self.features(ph, am), self.rollout(ph, am)
 
+    def close(self):
+        self.sim.close()
+
 
 @dataclasses.dataclass
 class Standardiser:

@@ -127,13 +127,22 @@ def test_positions_cube_contact_window():
     assert worst <= X_TOL
 
 
+def run_fp32_state(sys_, x, v, n0, steps):
+    """The oracle's steps with its state rounded to FP32 after each one: what storing the
+    state in FP32 alone does to a trajectory (the arithmetic stays FP64)."""
+    for n in range(n0, n0 + steps):
+        x, v = P.step(sys_, x, v, n)
+        x, v = x.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64)
+    return x, v
+
+
 def test_positions_quadruped_1000():
-    """The actuated quadruped is sensitive: the FP64 oracle started from the device's own FP32
-    initial state drifts from the exact start by ~3e-4 of the bbox by step 900.  The 1e-4 bar
-    holds over steps 0-400 (where that floor is ~1e-6); beyond, the device must stay within a
-    small multiple of the floor the dynamics themselves impose on its representation."""
+    """The actuated quadruped is chaotic: an FP64 oracle that merely stores its state in FP32
+    after every step leaves the exact oracle by ~1e-5 of the bbox at step 200 and ~2e-3 by step
+    900, so no FP32-state implementation can hold 1e-4 over 1000 steps.  The 1e-4 bar holds
+    over steps 0-400; beyond, the device must stay within 10x that FP32-state floor."""
     w = W.quadruped()
-    say("case: quadruped steps 0-1000 (actuated, contact) vs the sensitivity floor")
+    say("case: quadruped steps 0-1000 (actuated, contact) vs the FP32-state floor")
     lat, sys_, x0 = oracle_problem(w)
     sim, _, _ = PR.create(w, x0=x0, flags=CR.CHECK_LAYOUT)
     x_dev0, _, _ = CR.cronos_read_state(sim)          # the device's FP32 start, widened
@@ -141,15 +150,15 @@ def test_positions_quadruped_1000():
     xb, vb = x_dev0.copy(), np.zeros_like(x0)
     for n in range(0, 1000, 100):
         xa, va = P.run(sys_, xa, va, n, 100)
-        xb, vb = P.run(sys_, xb, vb, n, 100)
+        xb, vb = run_fp32_state(sys_, xb, vb, n, 100)
         CR.cronos_step(sim, 100)
         xg, _, _ = CR.cronos_read_state(sim)
         e, floor = position_error(xg, xa), position_error(xb, xa)
-        say(f"  step {n + 100}: device err {e:.3e}, floor {floor:.3e}")
+        say(f"  step {n + 100}: device err {e:.3e}, FP32-state floor {floor:.3e}")
         if n + 100 <= 400:
             assert e <= X_TOL
         else:
-            assert e <= max(X_TOL, 30.0 * floor)
+            assert e <= max(X_TOL, 10.0 * floor)
 
 
 def test_positions_cantilever_slab_1000():
@@ -179,7 +188,7 @@ def test_population_full_size_sampled():
     """The full 1024-robot population (about 11M masses) stepped together on the device,
     300 steps in the benchmark's launch configuration; three sampled robots are re-simulated
     alone by the oracle and compared (the robots are independent bodies).  Actuated contact
-    dynamics are sensitive, so the bar is max(1e-4, 30 x the FP32-rounding floor)."""
+    dynamics are sensitive, so the bar is max(1e-4, 10 x the FP32-state floor)."""
     w = W.population(1024)
     say("case: population 1024 robots, 300 steps, robots 0/511/1023 re-simulated by the oracle")
     sim, lat, x0 = PR.create(w)
@@ -196,10 +205,10 @@ def test_population_full_size_sampled():
         assert e - s == olat.n_masses
         assert np.array_equal(x0[s:e], ox0)
         xa, va = P.run(osys, ox0.copy(), np.zeros_like(ox0), 0, 300)
-        xb, vb = P.run(osys, x0_dev[s:e], np.zeros_like(ox0), 0, 300)
+        xb, vb = run_fp32_state(osys, x0_dev[s:e], np.zeros_like(ox0), 0, 300)
         err, floor = position_error(xg[s:e], xa), position_error(xb, xa)
-        say(f"  robot {r}: {e - s} masses, err {err:.3e}, floor {floor:.3e}")
-        assert err <= max(X_TOL, 30.0 * floor)
+        say(f"  robot {r}: {e - s} masses, err {err:.3e}, FP32-state floor {floor:.3e}")
+        assert err <= max(X_TOL, 10.0 * floor)
 
 
 # ------------------------------------------------------------------------- determinism, invariants
@@ -207,16 +216,19 @@ def test_population_full_size_sampled():
 def test_bitwise_repeatable_and_block_size_independent():
     w = W.quadruped()
     say("case: determinism, quadruped 300 steps: workgroup sizes, batches, launch forms, graph/plain, "
-        "table/explicit parameters")
-    outs = []
+        "split/table/explicit step forms")
+    outs, forms = [], set()
     for blk, flags, batch, pers in ((256, 0, 4, -1), (256, 0, 4, -1), (512, 0, 2, -1), (1024, 0, 8, -1),
                                     (256, CR.NO_GRAPH, 4, -1), (64, 0, 4, -1), (256, 0, 4, 1), (128, 0, 8, 1),
+                                    (256, CR.SPLIT, 4, -1), (1024, CR.SPLIT, 2, 1), (64, CR.SPLIT, 8, -1),
                                     (256, CR.NO_TABLE, 4, -1), (512, CR.NO_TABLE, 8, 1)):
         sim, _, _ = PR.create(w, block_masses=blk, flags=flags, batch=batch, persistent=pers)
+        forms.add(CR.cronos_launch_config(sim)["step_form"])
         CR.cronos_step(sim, 300)
         xg, vg, _ = CR.cronos_read_state(sim)
         outs.append((xg, vg))
         sim.close()
+    assert forms == {"split", "table", "explicit"}
     for xg, vg in outs[1:]:
         assert np.array_equal(xg, outs[0][0]) and np.array_equal(vg, outs[0][1])
 
@@ -312,20 +324,23 @@ def test_pinned_masses_do_not_move_and_state_roundtrip():
 
 
 def test_far_from_origin_and_near_plane_accuracy():
-    """The same strained cube placed far from the origin, straddling the coordinate planes,
-    and with the plain-difference fast path forced off: per-step forces meet the bar in every
-    placement (the device chooses exact differences wherever coordinates come near zero)."""
+    """The same strained cube placed far from the origin and straddling the coordinate planes,
+    in the shifted device frame (x, y shifted; z kept, near the contact plane: exact-z
+    wavefronts), in the caller's frame (NO_SHIFT: exact differences on all axes near the
+    planes), and with the exact differences forced off (FAST_DIFF, reported only): per-step
+    forces meet the bar in every placement."""
     base = W.cube_drop(6)
-    for origin in ((0.0, 0.0, 0.05), (-0.03, -0.02, 0.05), (37.0, -12.5, 0.05)):
-        w = W.Workload(**{**base.__dict__, "origin": origin})
+    for origin, ground in (((0.0, 0.0, 0.05), True), ((-0.03, -0.02, 0.05), True), ((37.0, -12.5, 0.05), True),
+                           ((-0.03, -0.02, -0.025), False)):
+        w = W.Workload(**{**base.__dict__, "origin": origin, "ground": ground})
         lat, sys_, x0 = oracle_problem(w)
-        for flags in (0, CR.FAST_DIFF):
+        for flags in (0, CR.NO_SHIFT, CR.FAST_DIFF | CR.NO_SHIFT):
             sim, _, _ = PR.create(w, x0=x0, flags=flags)
             CR.cronos_step(sim, 200)
             xg, _, _ = CR.cronos_read_state(sim)
             e, _ = force_error(CR.cronos_eval_forces(sim), sys_, xg, 200 * w.dt)
             say(f"  origin {origin} flags {flags}: force err {e:.2e}")
-            if flags == 0:
+            if not flags & CR.FAST_DIFF:
                 assert e <= F_TOL
             sim.close()
 
