@@ -87,6 +87,66 @@ def cpu_baseline(workload, steps: int):
                       f"({lat.n_masses} masses, {lat.n_springs} springs), single thread, {dt:.1f} s"}
 
 
+def adjoint_bench(args) -> dict:
+    """Gait gradient of the actuated quadruped: forward rollout of 2000 steps keeping a
+    checkpoint every 100 steps, then the adjoint (segments recomputed from the checkpoints),
+    against the plain forward rollout on HIP graphs."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2207_09334_amd import autograd as AG
+    from paper_2207_09334_amd import cronos as CR
+    from paper_2207_09334_amd import problem as PR
+
+    w = W.quadruped()
+    stream = torch.cuda.Stream()
+    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream)
+    v0 = np.zeros_like(x0)
+    lw = AG.forward_displacement_weights(lat.mass)
+    T, K = args.adjoint_steps, 100
+    ph, am = np.asarray(w.phase, float), np.asarray(w.amp, float)
+
+    def plain():
+        CR.cronos_set_state(sim, x0, v0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        CR.cronos_step(sim, T)
+        CR.cronos_read_state(sim)                 # blocks until the rollout is done
+        return time.perf_counter() - t0
+
+    def grad():
+        CR.cronos_set_state(sim, x0, v0, 0)
+        CR.cronos_set_actuation(sim, ph, am, w.freq_hz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = CR.cronos_rollout(sim, T, K, lw)
+        t1 = time.perf_counter()
+        dp, da = CR.cronos_rollout_backward(sim)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, loss, dp, da
+
+    CR.cronos_set_actuation(sim, ph, am, w.freq_hz)
+    plain()
+    grad()                                        # warm-up (allocations, graphs)
+    t_plain = min(plain() for _ in range(3))
+    runs = [grad() for _ in range(3)]
+    t_fwd = min(r[0] for r in runs)
+    t_bwd = min(r[1] for r in runs)
+    _, _, loss, dp, da = runs[-1]
+    repeat = all(np.array_equal(r[3], dp) and np.array_equal(r[4], da) for r in runs)
+    return {
+        "metric": "adjoint gait gradient: gradients/s (forward with checkpoints + backward)",
+        "value": 1.0 / (t_fwd + t_bwd), "unit": "gradients/s", "higher_is_better": True, "dtype": "f32 (FP64 parameter sums)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_masses": int(lat.n_masses), "n_springs": int(len(lat.ends)),
+                   "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph))},
+        "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
+        "gradient_over_plain_forward": (t_fwd + t_bwd) / t_plain, "loss": loss,
+        "bitwise_repeatable": bool(repeat),
+    }
+
+
 def surrogate_bench(args) -> dict:
     """Surrogate screening vs the plain batched simulator.  Morphology pools of `pool` robots
     (seed 4, disjoint robot-index ranges) are each simulated under `draws` actuation draws
@@ -179,7 +239,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
-    ap.add_argument("--workload", choices=("cantilever", "population", "surrogate"), default="cantilever")
+    ap.add_argument("--workload", choices=("cantilever", "population", "surrogate", "adjoint"), default="cantilever")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint: rollout length")
     ap.add_argument("--pool", type=int, default=1024, help="surrogate: robots per morphology pool")
     ap.add_argument("--pools", type=int, default=8, help="surrogate: training pools (disjoint robots)")
     ap.add_argument("--held-pools", type=int, default=1, help="surrogate: held-out pools")
@@ -201,6 +262,9 @@ def main():
 
     if args.workload == "surrogate":
         print(json.dumps(surrogate_bench(args)), flush=True)
+        return
+    if args.workload == "adjoint":
+        print(json.dumps(adjoint_bench(args)), flush=True)
         return
 
     import workloads as W
