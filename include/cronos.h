@@ -209,7 +209,9 @@ void cronos_destroy(cronos_sim sim);
 
 /* Actuation (rest length of a spring of group g in body b at t_n = n dt:
  * L0 (1 + amp[b*G+g] sin(2 pi freq_hz t_n + phase[b*G+g]))).  phase, amp: host
- * [n_bodies*n_groups], copied.  Errors: EINVAL (sim has no groups). */
+ * [n_bodies*n_groups], copied (held in FP32 on the device; the period fraction frac(n f dt)
+ * is formed exactly in 64-bit fixed point, so the phase stays within ~1e-7 rad of its
+ * FP64 value at any step).  Errors: EINVAL (sim has no groups, non-finite values). */
 cronos_status cronos_set_actuation(cronos_sim sim, const double* phase, const double* amp,
                                    double freq_hz);
 
