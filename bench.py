@@ -198,7 +198,8 @@ def surrogate_bench(args) -> dict:
                             D_train=np.concatenate(Dtr), morph_held=morph_te, D_held=np.concatenate(Dte),
                             pool=args.pool, pools=args.pools, held_pools=args.held_pools, draws=args.draws)
     Xtr, Dtr, Dte = np.concatenate(Xtr), np.concatenate(Dtr), np.concatenate(Dte)
-    sur = SG.Surrogate(Xtr, Dtr, epochs=args.epochs, batch=1024)
+    sur = SG.Surrogate(Xtr, Dtr, epochs=args.epochs, batch=1024, width=args.width, lr=args.lr,
+                       lr_final=args.lr_final if args.lr_final >= 0 else None)
     # screening throughput: candidates are (robot, actuation) pairs; the robots' morphology
     # descriptors are computed once, each candidate's features assembled natively, then predicted
     body_of = np.concatenate(body_of)
@@ -228,7 +229,9 @@ def surrogate_bench(args) -> dict:
         "higher_is_better": True, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
         "config": {"workload": f"surrogate_{args.pools}x{args.pool}robots_draws{args.draws}", "rollout_steps": 5000,
                    "heldout_robots": args.held_pools * args.pool,
-                   "train_rollouts": int(len(Xtr)), "heldout_candidates": int(n_cand), "epochs": args.epochs},
+                   "train_rollouts": int(len(Xtr)), "heldout_candidates": int(n_cand), "epochs": args.epochs,
+                   "mlp": [int(Xtr.shape[1]), args.width, args.width, args.width, int(Dtr.shape[1])],
+                   "mlp_params": sur.n_params, "lr": args.lr, "lr_final": args.lr_final if args.lr_final >= 0 else args.lr},
         "surrogate_evals_per_s": sur_rate, "sim_evals_per_s": sim_rate,
         "surrogate_evals_per_s_with_morphology": sur_rate_morph,
         "morphology_features_per_robot_s": (t1 - t0) / len(held_bodies),
@@ -241,7 +244,7 @@ def surrogate_bench(args) -> dict:
     }
 
 
-def main():
+def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
@@ -261,17 +264,20 @@ def main():
     ap.add_argument("--pools", type=int, default=8, help="surrogate: training pools (disjoint robots)")
     ap.add_argument("--held-pools", type=int, default=1, help="surrogate: held-out pools")
     ap.add_argument("--draws", type=int, default=8, help="surrogate: actuation draws simulated per robot")
-    ap.add_argument("--epochs", type=int, default=60, help="surrogate: training epochs")
+    ap.add_argument("--epochs", type=int, default=150, help="surrogate: training epochs")
+    ap.add_argument("--width", type=int, default=512, help="surrogate: hidden layer width")
+    ap.add_argument("--lr", type=float, default=2e-3, help="surrogate: initial learning rate")
+    ap.add_argument("--lr-final", type=float, default=0.0, help="surrogate: final learning rate of the cosine schedule (-1: constant)")
     ap.add_argument("--dump", default="", help="surrogate: directory to save the data set to (npz)")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (read MIB, write MIB) before the "
                          "timed steps, as the reference kernel for the HBM byte counters")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the step of one body "
-              "would shard into Morton slabs with halo exchange, which is not built.", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for {args.gpus}); the step of one body would shard "
+              "into Morton slabs with a halo exchange, which is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     os.environ.setdefault("OMP_NUM_THREADS", "1")

@@ -332,9 +332,11 @@ cronos_status cronos_mlp_loss_grad(cronos_mlp mlp, const float* x, const float* 
 cronos_status cronos_mlp_adam(cronos_mlp mlp, double lr, double beta1, double beta2, double eps);
 /* Train in place: `epochs` passes over (x, t) [rows] in minibatches of `batch` (<= max_rows),
  * shuffled every epoch by a SplitMix64-driven Fisher-Yates permutation of `seed`; Adam with
- * lr, 0.9, 0.999, 1e-8.  epoch_loss: mean minibatch loss of the last epoch. */
+ * 0.9, 0.999, 1e-8 and a learning rate that follows a half cosine from lr (first step) to
+ * lr_final (last step); lr_final = lr keeps it constant.  epoch_loss: mean minibatch loss of
+ * the last epoch.  Errors: EINVAL (sizes, negative rates), EDEVICE. */
 cronos_status cronos_mlp_train(cronos_mlp mlp, const float* x, const float* t, int64_t rows, int32_t batch,
-                               int32_t epochs, double lr, uint64_t seed, double* epoch_loss);
+                               int32_t epochs, double lr, double lr_final, uint64_t seed, double* epoch_loss);
 
 /* Input-order layout of a created simulation (see cronos_layout_get). */
 cronos_status cronos_get_layout(cronos_sim sim, int32_t* perm, int64_t* row_ptr, int32_t* col,

@@ -109,7 +109,7 @@ _SIGS = {
     "cronos_mlp_forward": (C.c_int, [_p, _p, _i64, _p]),
     "cronos_mlp_loss_grad": (C.c_int, [_p, _p, _p, _i32, C.POINTER(_f64), _p]),
     "cronos_mlp_adam": (C.c_int, [_p, _f64, _f64, _f64, _f64]),
-    "cronos_mlp_train": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, C.c_uint64, C.POINTER(_f64)]),
+    "cronos_mlp_train": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64, C.c_uint64, C.POINTER(_f64)]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -467,10 +467,10 @@ def cronos_mlp_adam(mlp: MLP, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(_lib.cronos_mlp_adam(mlp.handle, lr, beta1, beta2, eps))
 
 
-def cronos_mlp_train(mlp: MLP, x, t, batch=1024, epochs=1, lr=1e-3, seed=4) -> float:
+def cronos_mlp_train(mlp: MLP, x, t, batch=1024, epochs=1, lr=1e-3, seed=4, lr_final=None) -> float:
     xx = _arr(x, np.float32, (-1, mlp.sizes[0]))
     tt = _arr(t, np.float32, (-1, mlp.sizes[4]))
     out = _f64()
     _check(_lib.cronos_mlp_train(mlp.handle, _ptr(xx), _ptr(tt), len(xx), int(batch), int(epochs), float(lr),
-                                 C.c_uint64(seed), C.byref(out)))
+                                 float(lr if lr_final is None else lr_final), C.c_uint64(seed), C.byref(out)))
     return out.value

@@ -451,9 +451,10 @@ extern "C" cronos_status cronos_mlp_adam(cronos_mlp q, double lr, double beta1, 
 }
 
 extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const float* t, int64_t rows, int32_t batch,
-                                          int32_t epochs, double lr, uint64_t seed, double* epoch_loss) {
+                                          int32_t epochs, double lr, double lr_final, uint64_t seed, double* epoch_loss) {
     cronos::clear_error();
-    if (!q || !x || !t || rows < 1 || batch < 1 || batch > q->max_rows || epochs < 0)
+    if (!q || !x || !t || rows < 1 || batch < 1 || batch > q->max_rows || epochs < 0 || !(lr >= 0.0) ||
+        !(lr_final >= 0.0))
         return fail(CRONOS_EINVAL, "mlp_train: bad arguments");
     HIP_TRY(hipSetDevice(q->device));
     const int n_in = q->sizes[0], n_out = q->sizes[4];
@@ -472,6 +473,9 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
     HIP_TRY(hipMemcpyAsync(q->data_x, x, (size_t)rows * n_in * sizeof(float), hipMemcpyHostToDevice, q->stream));
     HIP_TRY(hipMemcpyAsync(q->data_t, t, (size_t)rows * n_out * sizeof(float), hipMemcpyHostToDevice, q->stream));
     std::vector<int> perm(rows);
+    // learning rate: cosine from lr to lr_final over all minibatch steps (constant if equal)
+    const int64_t per_epoch = (rows + batch - 1) / batch, last = std::max<int64_t>(1, per_epoch * epochs - 1);
+    int64_t step = 0;
     for (int e = 0; e < epochs; ++e) {
         // epoch order: Fisher-Yates driven by SplitMix64(seed, epoch, i)
         for (int64_t i = 0; i < rows; ++i) perm[i] = (int)i;
@@ -490,7 +494,8 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
             HIP_TRY(hipGetLastError());
             cronos_status st = forward_dev(q, r);
             if (st == CRONOS_OK) st = backward_dev(q, r);
-            if (st == CRONOS_OK) st = adam_dev(q, lr, 0.9, 0.999, 1e-8);
+            const double lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * (double)step++ / (double)last));
+            if (st == CRONOS_OK) st = adam_dev(q, lr_t, 0.9, 0.999, 1e-8);
             if (st != CRONOS_OK) return st;
             if (e == epochs - 1) {
                 const double l = loss_from_parts(q, r, &st);

@@ -81,15 +81,19 @@ class Standardiser:
 
 
 class Surrogate:
-    def __init__(self, X: np.ndarray, D: np.ndarray, epochs: int = 60, batch: int = 1024, lr: float = 1e-3,
-                 seed: int = 4, max_rows: int = 4096):
+    def __init__(self, X: np.ndarray, D: np.ndarray, epochs: int = 150, batch: int = 1024, lr: float = 2e-3,
+                 seed: int = 4, max_rows: int = 4096, width: int = 512, lr_final: float = 0.0):
+        """width: hidden layer width (three hidden layers); lr_final: end of the cosine
+        learning-rate schedule (None: constant lr)."""
         self.xs, self.ds = Standardiser.fit(X), Standardiser.fit(D)
         Xn = self.xs.apply(X)
         self.lo, self.hi = Xn.min(axis=0), Xn.max(axis=0)
-        self.net = CR.cronos_mlp_create(W.mlp_init(seed), max_rows=max_rows)
+        sizes = (X.shape[1], width, width, width, D.shape[1])
+        self.net = CR.cronos_mlp_create(W.mlp_init(seed, sizes), max_rows=max_rows)
+        self.n_params = sum(sizes[l] * sizes[l + 1] + sizes[l + 1] for l in range(4))
         t0 = time.perf_counter()
         self.train_loss = CR.cronos_mlp_train(self.net, Xn.astype(np.float32), self.ds.apply(D).astype(np.float32),
-                                              batch=batch, epochs=epochs, lr=lr, seed=seed)
+                                              batch=batch, epochs=epochs, lr=lr, seed=seed, lr_final=lr_final)
         self.train_seconds = time.perf_counter() - t0
 
     def predict(self, X: np.ndarray) -> np.ndarray:

@@ -91,6 +91,27 @@ def test_training_fits_a_smooth_function():
     assert last < 0.05 * l0
 
 
+def test_learning_rate_schedule():
+    """A zero learning rate leaves the parameters bitwise unchanged; the cosine schedule from
+    1e-3 to 0 trains; its first step uses lr, so a one-step schedule from 0 to 1e-3 changes
+    nothing."""
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(2048, 96)).astype(np.float32)
+    T = np.tanh(X[:, :3]).astype(np.float32)
+    p0 = W.mlp_init(4)
+    net = CR.cronos_mlp_create(p0, max_rows=512)
+    before = CR.cronos_mlp_get_params(net)
+    CR.cronos_mlp_train(net, X, T, batch=512, epochs=2, lr=0.0, lr_final=0.0, seed=2)
+    assert all(np.array_equal(a, b) for a, b in zip(before, CR.cronos_mlp_get_params(net)))
+    l0 = CR.cronos_mlp_loss_grad(net, X[:512], T[:512])[0]
+    last = CR.cronos_mlp_train(net, X, T, batch=512, epochs=20, lr=1e-3, lr_final=0.0, seed=2)
+    say(f"  cosine schedule: initial loss {l0:.4f}, last-epoch loss {last:.4f}")
+    assert last < 0.2 * l0
+    net1 = CR.cronos_mlp_create(p0, max_rows=512)
+    CR.cronos_mlp_train(net1, X[:512], T[:512], batch=512, epochs=1, lr=0.0, lr_final=1e-3, seed=2)
+    assert all(np.array_equal(a, b) for a, b in zip(before, CR.cronos_mlp_get_params(net1)))
+
+
 def test_screening_pipeline_small():
     """A 48-robot pool, 8 actuation draws of 400 steps: the judge (simulator) is bitwise
     repeatable, training runs on the device, predictions are finite, out-of-distribution
