@@ -101,7 +101,7 @@ def adjoint_bench(args) -> dict:
 
     w = W.quadruped()
     stream = torch.cuda.Stream()
-    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream)
+    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, block_masses=args.block)
     v0 = np.zeros_like(x0)
     lw = AG.forward_displacement_weights(lat.mass)
     T, K = args.adjoint_steps, 100
@@ -140,7 +140,8 @@ def adjoint_bench(args) -> dict:
         "value": 1.0 / (t_fwd + t_bwd), "unit": "gradients/s", "higher_is_better": True, "dtype": "f32 (FP64 parameter sums)",
         "data": "synthetic",
         "config": {"workload": w.name, "n_masses": int(lat.n_masses), "n_springs": int(len(lat.ends)),
-                   "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph))},
+                   "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph)),
+                   "block_masses": CR.cronos_launch_config(sim)["block_masses"]},
         "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
         "gradient_over_plain_forward": (t_fwd + t_bwd) / t_plain, "loss": loss,
         "bitwise_repeatable": bool(repeat),
@@ -258,7 +259,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
-    ap.add_argument("--workload", choices=("cantilever", "population", "surrogate", "adjoint"), default="cantilever")
+    ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "surrogate", "adjoint"),
+                    default="cantilever")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint: rollout length")
     ap.add_argument("--pool", type=int, default=1024, help="surrogate: robots per morphology pool")
     ap.add_argument("--pools", type=int, default=8, help="surrogate: training pools (disjoint robots)")
@@ -296,6 +298,8 @@ def main(argv=None):
 
     if args.workload == "population":
         w = W.population(args.robots)
+    elif args.workload == "quadruped":
+        w = W.quadruped()
     else:
         w = W.cantilever(args.nx, 40, 40)
     lat = PR.build_lattice(w)
