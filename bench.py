@@ -256,11 +256,14 @@ def main(argv=None):
     ap.add_argument("--fast-diff", action="store_true", help="skip the exact coordinate difference")
     ap.add_argument("--no-table", action="store_true", help="explicit per-entry (k, L0) instead of the table")
     ap.add_argument("--split", action="store_true", help="split step form (spring pass + gather pass)")
+    ap.add_argument("--integrator", choices=("euler", "verlet"), default="euler",
+                    help="symplectic Euler (default) or Verlet, eqs. (5)-(6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
-    ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "surrogate", "adjoint"),
+    ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "surrogate", "adjoint"),
                     default="cantilever")
+    ap.add_argument("--resident", action="store_true", help="one-workgroup multi-step form (systems of <= 1024 masses)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint: rollout length")
     ap.add_argument("--pool", type=int, default=1024, help="surrogate: robots per morphology pool")
     ap.add_argument("--pools", type=int, default=8, help="surrogate: training pools (disjoint robots)")
@@ -300,12 +303,15 @@ def main(argv=None):
         w = W.population(args.robots)
     elif args.workload == "quadruped":
         w = W.quadruped()
+    elif args.workload == "cube":
+        w = W.cube_drop()
     else:
         w = W.cantilever(args.nx, 40, 40)
     lat = PR.build_lattice(w)
     stream = torch.cuda.Stream()
     flags = ((CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0) |
-             (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0))
+             (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0) |
+             (CR.VERLET if args.integrator == "verlet" else 0) | (CR.RESIDENT if args.resident else 0))
     sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block, batch=args.batch,
                           tune_steps=20 if args.tune else 0)
     info = CR.cronos_info(sim)
@@ -364,7 +370,8 @@ def main(argv=None):
         "config": {"workload": w.name, "n_bodies": len(w.bodies), "n_masses": N, "n_springs": S, "dt": w.dt,
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
                    "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
-                   "exact_difference": not args.fast_diff, "step_form": launch["step_form"]},
+                   "exact_difference": not args.fast_diff, "step_form": launch["step_form"],
+                   "integrator": args.integrator},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": b_step},

@@ -54,6 +54,16 @@ typedef enum {
 #define CRONOS_SPLIT          0x40u  /* split step form: a spring pass evaluates each spring once
                                         per workgroup into LDS, then a gather pass sums them
                                         (default: every spring evaluated from both ends)    */
+#define CRONOS_VERLET         0x80u  /* integrate with Verlet, eqs. (5)-(6), instead of symplectic
+                                        Euler: run in velocity form, the first step after create
+                                        or set_state kicks for dt / 2 (eq. (5)) and the velocity
+                                        held is (x_{n+1} - x_n) / dt; contact friction and
+                                        damping act on it as in the Euler step.  Not with
+                                        cronos_rollout (its adjoint is of the Euler step)    */
+#define CRONOS_RESIDENT       0x100u /* a system of at most 1024 masses runs in one workgroup that
+                                        keeps it in LDS and takes up to 4096 steps per launch
+                                        (compact table form needed; ignored otherwise, see
+                                        cronos_launch_config)                                 */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -245,6 +255,7 @@ cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs,
 #define CRONOS_FORM_EXPLICIT 0  /* (slot, k, L0) per entry, every spring evaluated at both ends  */
 #define CRONOS_FORM_TABLE    1  /* 32-bit entries indexing the table of distinct (k, L0) pairs    */
 #define CRONOS_FORM_SPLIT    2  /* spring pass (each spring once per workgroup) + gather pass     */
+#define CRONOS_FORM_RESIDENT 3  /* table form, the whole system in one workgroup, many steps per launch */
 cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
                                    int32_t* step_form);
 

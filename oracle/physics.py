@@ -18,6 +18,8 @@ What one time step computes, in the paper's order:
    as printed advances x with v_n, which is not energy-stable; the paper reports energy
    conservation, which the symplectic variant gives;
 8. pinned (fixed) masses keep x and get v' = 0.
+
+The Verlet integrator of eqs. (5)-(6) is ``verlet_start`` / ``verlet_step``.
 """
 from __future__ import annotations
 
@@ -120,27 +122,73 @@ def forces(sys: System, x: np.ndarray, t: float) -> np.ndarray:
     return f
 
 
-def step(sys: System, x: np.ndarray, v: np.ndarray, n: int):
-    """One time step from t_n = n dt; returns (x_{n+1}, v_{n+1})."""
-    t = n * sys.dt
-    f = forces(sys, x, t)
-    vs = v + sys.dt * f / sys.mass[:, None]
+def friction(sys: System, x: np.ndarray, vs: np.ndarray, h: float) -> np.ndarray:
+    """Coulomb clamp of the tangential velocity of contacting masses for a kick of length h:
+    it loses c = mu F_n h / m of its magnitude, or stops if it is smaller (in place)."""
     if sys.ground:
         fn = contact_normal(sys, x)
         touching = fn > 0
         if touching.any():
-            c = sys.ground_mu * fn[touching] * sys.dt / sys.mass[touching]
+            c = sys.ground_mu * fn[touching] * h / sys.mass[touching]
             vt = vs[touching, :2]
             speed = np.sqrt((vt * vt).sum(axis=1))
             slide = speed > c
             scale = np.zeros_like(speed)
             scale[slide] = (speed[slide] - c[slide]) / speed[slide]
             vs[touching, :2] = vt * scale[:, None]
+    return vs
+
+
+def step(sys: System, x: np.ndarray, v: np.ndarray, n: int):
+    """One time step from t_n = n dt; returns (x_{n+1}, v_{n+1})."""
+    t = n * sys.dt
+    f = forces(sys, x, t)
+    vs = friction(sys, x, v + sys.dt * f / sys.mass[:, None], sys.dt)
     vn = (1.0 - sys.damping) * vs
     xn = x + sys.dt * vn
     xn[sys.pinned] = x[sys.pinned]
     vn[sys.pinned] = 0.0
     return xn, vn
+
+
+# ---------------------------------------------------------------- Verlet (eqs. (5)-(6))
+#
+# Eq. (5) starts from (x_0, v_0): x_1 = x_0 + dt v_0 + dt^2 / (2 m) f(0, x_0); eq. (6) then
+# advances x_{n+1} = 2 x_n - x_{n-1} + dt^2 / m f(t_n, x_n).  The paper does not say how
+# contact friction and damping enter; they act, as in the Euler step, on the velocity of the
+# interval, w = (x_{n+1} - x_n) / dt (before them: w = (x_n - x_{n-1}) / dt + dt f / m, which
+# is eq. (6) itself), with a kick of dt / 2 in the first step.  Without contact and damping
+# both functions reduce to eqs. (5) and (6).
+
+def verlet_start(sys: System, x0: np.ndarray, v0: np.ndarray, n0: int = 0) -> np.ndarray:
+    """Eq. (5): x_1 from (x_0, v_0) at t_{n0}."""
+    h = 0.5 * sys.dt
+    f = forces(sys, x0, n0 * sys.dt)
+    w = friction(sys, x0, v0 + h * f / sys.mass[:, None], h)
+    w = (1.0 - sys.damping) * w
+    x1 = x0 + sys.dt * w
+    x1[sys.pinned] = x0[sys.pinned]
+    return x1
+
+
+def verlet_step(sys: System, x_prev: np.ndarray, x: np.ndarray, n: int) -> np.ndarray:
+    """Eq. (6): x_{n+1} from x_{n-1} and x_n at t_n = n dt."""
+    f = forces(sys, x, n * sys.dt)
+    if not sys.ground and sys.damping == 0.0:
+        xn = 2.0 * x - x_prev + sys.dt ** 2 * f / sys.mass[:, None]
+    else:
+        w = friction(sys, x, (x - x_prev) / sys.dt + sys.dt * f / sys.mass[:, None], sys.dt)
+        xn = x + sys.dt * (1.0 - sys.damping) * w
+    xn[sys.pinned] = x[sys.pinned]
+    return xn
+
+
+def run_verlet(sys: System, x0: np.ndarray, v0: np.ndarray, n0: int, steps: int):
+    """Positions after ``steps`` Verlet steps from (x_0, v_0) at step n0; returns (x_n, x_{n-1})."""
+    x_prev, x = x0, verlet_start(sys, x0, v0, n0)
+    for s in range(1, steps):
+        x_prev, x = x, verlet_step(sys, x_prev, x, n0 + s)
+    return (x, x_prev) if steps > 0 else (x0, x0)
 
 
 def run(sys: System, x: np.ndarray, v: np.ndarray, n0: int, steps: int, every: int = 0):

@@ -7,7 +7,8 @@
 namespace cronos {
 
 struct StepParams {
-    float dt;
+    float dt;            // position update x' = x + dt v'
+    float dtv;           // velocity kick v* = v + dtv f / m (dt; dt / 2 in Verlet's first step)
     float damp;          // 1 - d
     float gx, gy, gz;
     float ground_z, ground_k, ground_mu;
@@ -45,6 +46,7 @@ struct DeviceArrays {
     uint16_t* sp_grp = nullptr;          //   their local actuation factor indices,
     int32_t* sp_ptr = nullptr;           //   per-workgroup record ranges
     int32_t max_sp = 0;                  //   and the largest record count of a workgroup
+    int32_t resident = 0;                // one workgroup holds the system (see launch_resident)
     uint16_t* grp = nullptr;             // per entry index into factor[], or null
     int32_t* halo_ptr = nullptr;
     int32_t* halo_idx = nullptr;
@@ -77,6 +79,11 @@ hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipS
 // The step with explicit buffers; vstar (optional) receives the velocity before friction/damping.
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
                           float* vstar, const StepParams& p, hipStream_t st);
+// `steps` steps of a system held by one workgroup (resident form; table form, block >= n):
+// positions stay in LDS between steps; the first step kicks for dtv0.  Reads x[cur], v[cur],
+// writes x[cur ^ 1], v[cur ^ 1]; advances the device step counter by `steps`.
+hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, float dtv0, unsigned long long cycles,
+                           int steps, hipStream_t st);
 // Workgroups of a persistent launch that are resident at once on the device (multiple of 8).
 hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid);
 // Actuation table for the device step counter (advancing it when advance != 0), or for the

@@ -397,8 +397,77 @@ __device__ __forceinline__ int difference_mode(float4 xi, float safe) {
 template <int BATCH>
 constexpr int kExactBatch = BATCH > 2 ? BATCH / 2 : BATCH;
 
+// Per-launch arguments of the resident form (see step_resident).
+struct ResidentArgs {
+    const float* __restrict__ phase;
+    const float* __restrict__ amp;
+    unsigned long long cycles;
+    long long* __restrict__ step_ctr;
+    int steps;
+    float dtv0;
+};
+
 // Step modes: explicit (k, L0) per entry, compact entries with the parameter table, split.
 enum : int { kExplicit = 0, kTable = 1, kSplit = 2 };
+
+// Elapsed fraction of an actuation period at step n, frac(n f dt), formed exactly in 64-bit
+// fixed point (n * cycles wraps modulo 2^64), and the factor 1 + A sin(2 pi u + phi).
+__device__ __forceinline__ float period_fraction(long long n, unsigned long long cycles) {
+    const unsigned long long frac = (unsigned long long)n * cycles;
+    return (float)(unsigned)(frac >> 32) * 0x1p-32f;
+}
+__device__ __forceinline__ float actuation_factor(float amp, float phase, float u) {
+    return __builtin_fmaf(amp, sinf(__builtin_fmaf(6.28318531f, u, phase)), 1.0f);
+}
+
+// Body forces, contact, friction, damping and the symplectic Euler update of one mass with
+// spring force f: v* = v + dtv a (v* is stored to vstar when given), Coulomb clamp, damping,
+// x' = x + dt v'; a fixed mass (1/m = 0) keeps x and gets v' = 0.  dtv is dt except in
+// Verlet's first step (dt / 2).
+__device__ __forceinline__ void integrate(const StepParams& p, float dtv, float4 xi, float fx, float fy, float fz,
+                                          const float* __restrict__ fext, float& vx, float& vy, float& vz,
+                                          float4& xo, float* __restrict__ vstar) {
+    const float inv_m = xi.w;
+    float ax = __builtin_fmaf(fx, inv_m, p.gx);
+    float ay = __builtin_fmaf(fy, inv_m, p.gy);
+    float az = __builtin_fmaf(fz, inv_m, p.gz);
+    if (fext) {
+        ax = __builtin_fmaf(fext[0], inv_m, ax);
+        ay = __builtin_fmaf(fext[1], inv_m, ay);
+        az = __builtin_fmaf(fext[2], inv_m, az);
+    }
+    float fn = 0.0f;
+    if (p.ground) {
+        const float pen = p.ground_z - xi.z;
+        fn = pen > 0.0f ? p.ground_k * pen : 0.0f;
+        az = __builtin_fmaf(fn, inv_m, az);
+    }
+    vx = __builtin_fmaf(dtv, ax, vx);
+    vy = __builtin_fmaf(dtv, ay, vy);
+    vz = __builtin_fmaf(dtv, az, vz);
+    if (vstar) {
+        vstar[0] = vx;
+        vstar[1] = vy;
+        vstar[2] = vz;
+    }
+    if (fn > 0.0f) {
+        // Coulomb clamp: the tangential speed loses mu F_n dtv / m, or stops
+        const float c = p.ground_mu * fn * dtv * inv_m;
+        const float sp = __builtin_sqrtf(vx * vx + vy * vy);
+        const float sc = sp > c ? (sp - c) / sp : 0.0f;
+        vx *= sc;
+        vy *= sc;
+    }
+    vx *= p.damp;
+    vy *= p.damp;
+    vz *= p.damp;
+    xo = make_float4(__builtin_fmaf(p.dt, vx, xi.x), __builtin_fmaf(p.dt, vy, xi.y), __builtin_fmaf(p.dt, vz, xi.z),
+                     inv_m);
+    if (inv_m == 0.0f) {  // fixed mass
+        xo = xi;
+        vx = vy = vz = 0.0f;
+    }
+}
 
 // One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
 // damping, symplectic Euler, fixed masses.
@@ -446,58 +515,16 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
     }
     const int i = base + own;
     if (i >= a.n) return;
-
-    const float inv_m = xi.w;
     float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
-    float ax = __builtin_fmaf(fx, inv_m, p.gx);
-    float ay = __builtin_fmaf(fy, inv_m, p.gy);
-    float az = __builtin_fmaf(fz, inv_m, p.gz);
-    if (a.fext) {
-        ax = __builtin_fmaf(a.fext[3 * i + 0], inv_m, ax);
-        ay = __builtin_fmaf(a.fext[3 * i + 1], inv_m, ay);
-        az = __builtin_fmaf(a.fext[3 * i + 2], inv_m, az);
-    }
-    float fn = 0.0f;
-    if (p.ground) {
-        const float pen = p.ground_z - xi.z;
-        fn = pen > 0.0f ? p.ground_k * pen : 0.0f;
-        az = __builtin_fmaf(fn, inv_m, az);
-    }
-    vx = __builtin_fmaf(p.dt, ax, vx);
-    vy = __builtin_fmaf(p.dt, ay, vy);
-    vz = __builtin_fmaf(p.dt, az, vz);
-    if (a.vstar_out) {
-        a.vstar_out[3 * i + 0] = vx;
-        a.vstar_out[3 * i + 1] = vy;
-        a.vstar_out[3 * i + 2] = vz;
-    }
-    if (fn > 0.0f) {
-        // Coulomb clamp: the tangential speed loses mu F_n dt / m, or stops
-        const float c = p.ground_mu * fn * p.dt * inv_m;
-        const float sp = __builtin_sqrtf(vx * vx + vy * vy);
-        const float sc = sp > c ? (sp - c) / sp : 0.0f;
-        vx *= sc;
-        vy *= sc;
-    }
-    vx *= p.damp;
-    vy *= p.damp;
-    vz *= p.damp;
-    float nx = __builtin_fmaf(p.dt, vx, xi.x);
-    float ny = __builtin_fmaf(p.dt, vy, xi.y);
-    float nz = __builtin_fmaf(p.dt, vz, xi.z);
-    if (inv_m == 0.0f) {  // fixed mass
-        nx = xi.x;
-        ny = xi.y;
-        nz = xi.z;
-        vx = vy = vz = 0.0f;
-    }
-    a.xout[i] = make_float4(nx, ny, nz, inv_m);
+    float4 xo;
+    integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+              a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+    a.xout[i] = xo;
     a.vout[3 * i + 0] = vx;
     a.vout[3 * i + 1] = vy;
     a.vout[3 * i + 2] = vz;
 }
 
-// One workgroup per block.
 template <bool ACT, bool EXACT, int BATCH, int MODE>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
@@ -520,6 +547,59 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
         step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b);
         __syncthreads();  // LDS is restaged for the next block
     }
+}
+
+// Resident form for a system that fits one workgroup (at most 1024 masses, one block, the
+// compact table form): K steps in one launch.  Positions stay in LDS, velocities in
+// registers; each step computes its actuation factors in place (the same formula as
+// actuation_kernel), gathers, integrates, and after a barrier overwrites the positions.  The
+// device step counter advances by K.  The first step kicks for dtv0 (Verlet's dt / 2).
+template <bool ACT, bool EXACT, int BATCH>
+__global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, ResidentArgs r) {
+    extern __shared__ float4 sx[];
+    const uint32_t tbase = table_base(a.lds_slots);
+    float4* st = reinterpret_cast<float4*>(reinterpret_cast<char*>(sx) + tbase);
+    float* sf = reinterpret_cast<float*>(st + a.n_table);
+    const int t = (int)threadIdx.x;
+    for (int q = t; q < a.n_table; q += a.block) st[q] = a.table[q];
+    sx[t] = t < a.n ? a.xin[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int own = a.lane_mass[t];
+    const bool live = own < a.n;
+    float vx = 0.f, vy = 0.f, vz = 0.f;
+    if (live) {
+        vx = a.vin[3 * own + 0];
+        vy = a.vin[3 * own + 1];
+        vz = a.vin[3 * own + 2];
+    }
+    const long long n0 = *r.step_ctr;
+    const int2 bg = ACT ? a.blk_groups[0] : make_int2(0, 0);
+    const float* fext = a.fext && live ? a.fext + 3 * own : nullptr;
+    const int s = t >> 6;
+    float4 xo = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < r.steps; ++k) {
+        if (ACT) {
+            const float u = period_fraction(n0 + k, r.cycles);
+            for (int q = t; q <= bg.y; q += a.block)
+                sf[q] = q ? actuation_factor(r.amp[bg.x + q - 1], r.phase[bg.x + q - 1], u) : 1.0f;
+        }
+        __syncthreads();  // positions of step k and its factors are in LDS
+        const float4 xi = sx[own];
+        float fx, fy, fz;
+        const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
+        if (mode == kPlain) gather_table<ACT, kPlain, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+        else if (mode == kExactZ) gather_table<ACT, kExactZ, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+        else gather_table<ACT, kExactAll, kExactBatch<BATCH>>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+        integrate(p, k == 0 ? r.dtv0 : p.dtv, xi, fx, fy, fz, fext, vx, vy, vz, xo, nullptr);
+        __syncthreads();  // every lane has read step k's positions
+        if (live) sx[own] = xo;
+    }
+    if (live) {
+        a.xout[own] = xo;
+        a.vout[3 * own + 0] = vx;
+        a.vout[3 * own + 1] = vy;
+        a.vout[3 * own + 2] = vz;
+    }
+    if (t == 0) *r.step_ctr = n0 + r.steps;
 }
 
 // Total force of eq. (2) + contact normal at the current state (same gather as the step).
@@ -574,10 +654,9 @@ actuation_kernel(const float* __restrict__ phase, const float* __restrict__ amp,
                  long long* __restrict__ step_ctr, unsigned* __restrict__ done, float* __restrict__ factor,
                  int n_factor, int advance, long long n_explicit) {
     const long long n = n_explicit >= 0 ? n_explicit : *step_ctr;
-    const unsigned long long frac = (unsigned long long)n * cycles;
-    const float u = (float)(unsigned)(frac >> 32) * 0x1p-32f;
+    const float u = period_fraction(n, cycles);
     const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (g < n_factor) factor[g] = __builtin_fmaf(amp[g], sinf(__builtin_fmaf(6.28318531f, u, phase[g])), 1.0f);
+    if (g < n_factor) factor[g] = actuation_factor(amp[g], phase[g], u);
     else if (g == n_factor) factor[g] = 1.0f;
     if (advance) {
         __syncthreads();
@@ -916,6 +995,20 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
     }
 #undef CRONOS_GO_M
 #undef CRONOS_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, float dtv0, unsigned long long cycles,
+                           int steps, hipStream_t st) {
+    StepArgs a{d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
+               d.lane_mass, d.factor, d.fext, nullptr, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr,
+               (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups};
+    ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr, steps, dtv0};
+    const size_t lds = step_lds_bytes(d);
+    const bool act = d.grp != nullptr, ex = p.exact != 0;
+    auto go = [&](auto k) { hipLaunchKernelGGL(k, dim3(1), dim3(d.block), lds, st, a, p, r); };
+    if (act) ex ? go(step_resident<true, true, 4>) : go(step_resident<true, false, 4>);
+    else ex ? go(step_resident<false, true, 4>) : go(step_resident<false, false, 4>);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ extern "C" const char* cronos_version(void) { return "cronos-gfx950 0.1"; }
 namespace {
 
 constexpr int kGraphSteps = 16;  // steps per captured graph (even: ping-pong parity preserved)
+constexpr int kResidentSteps = 4096;  // steps per launch of the resident form
 
 #define HIP_TRY(expr)                                                                             \
     do {                                                                                          \
@@ -87,6 +88,8 @@ struct cronos_sim_t {
     double dt = 0.0, omega = 0.0;
     unsigned long long cycles = 0;       // frac(f dt) * 2^64: period fraction per step
     bool actuated = false, use_graph = true;
+    bool verlet = false;                 // integrator of eqs. (5)-(6): first step kicks dt / 2
+    bool half_kick = false;              // the next step is Verlet's first
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::vector<float> inv_m;            // new order
     std::vector<uint16_t> h_grp;         // per entry factor index (actuated sims), for the adjoint reduction
@@ -364,6 +367,9 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     }
     if (batch == 0) batch = 4;
     if (persistent < 0) persistent = 0;
+    // the resident form holds the whole system in one workgroup
+    if ((d->flags & CRONOS_RESIDENT) && n <= 1024 && (block == 0 || block < n))
+        block = (int32_t)std::max<int64_t>(cronos::kSlice, (n + cronos::kSlice - 1) / cronos::kSlice * cronos::kSlice);
 
     auto* sim = new (std::nothrow) cronos_sim_t;
     if (!sim) return fail(CRONOS_ENOMEM, "create: out of memory");
@@ -736,6 +742,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             }
             TRY(upload(&D.table, tab.data(), tab.size()));
             D.n_table = (int32_t)htable.size();
+            D.resident = (d->flags & CRONOS_RESIDENT) && L.nblk == 1 && hsp_rec.empty() ? 1 : 0;
             if (sim->actuated) TRY(upload(&D.blk_groups, hblk_groups.data(), hblk_groups.size()));
             D.max_local_groups = max_local_groups;
         }
@@ -766,6 +773,9 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     }
     cronos::StepParams& P = sim->p;
     P.dt = (float)d->dt;
+    P.dtv = P.dt;
+    sim->verlet = (d->flags & CRONOS_VERLET) != 0;
+    sim->half_kick = sim->verlet;
     P.damp = (float)(1.0 - d->damping);
     P.gx = (float)d->gravity[0];
     P.gy = (float)d->gravity[1];
@@ -844,6 +854,30 @@ extern "C" cronos_status cronos_step(cronos_sim sim, int64_t n_steps) {
     if (n_steps < 0) return fail(CRONOS_EINVAL, "step: n_steps < 0");
     HIP_TRY(hipSetDevice(sim->device));
     int64_t left = n_steps;
+    if (sim->d.resident) {
+        // one launch runs up to kResidentSteps steps inside a single workgroup
+        float dtv0 = sim->half_kick ? 0.5f * sim->p.dt : sim->p.dtv;
+        while (left > 0) {
+            const int k = (int)std::min<int64_t>(left, kResidentSteps);
+            HIP_TRY(cronos::launch_resident(sim->d, sim->cur, sim->p, dtv0, sim->cycles, k, sim->stream));
+            sim->cur ^= 1;
+            left -= k;
+            dtv0 = sim->p.dtv;
+        }
+        if (n_steps > 0) sim->half_kick = false;
+        sim->step += n_steps;
+        return CRONOS_OK;
+    }
+    if (sim->half_kick && left > 0) {
+        // Verlet's first step (eq. (5)) kicks the velocity for dt / 2; the steps after it are
+        // eq. (6), which in velocity form is the same kernel with a full kick
+        sim->p.dtv = 0.5f * sim->p.dt;
+        const cronos_status st = enqueue_plain(sim, 1);
+        sim->p.dtv = sim->p.dt;
+        if (st != CRONOS_OK) return st;
+        sim->half_kick = false;
+        --left;
+    }
     if (sim->use_graph && sim->stream && left >= kGraphSteps) {
         TRY(ensure_graph(sim));
         while (left >= kGraphSteps) {
@@ -911,6 +945,7 @@ extern "C" cronos_status cronos_set_state(cronos_sim sim, const double* x, const
     long long ctr = step;
     HIP_TRY(hipMemcpy(sim->d.step_ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice));
     sim->step = step;
+    sim->half_kick = sim->verlet;   // Verlet restarts from (x_0, v_0): eq. (5)
     return CRONOS_OK;
 }
 
@@ -1000,6 +1035,7 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     cronos::clear_error();
     if (!sim || !loss_w || !loss) return fail(CRONOS_EINVAL, "rollout: NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(CRONOS_EINVAL, "rollout: need n_steps >= 0 and ckpt_every >= 1");
+    if (sim->verlet) return fail(CRONOS_EINVAL, "rollout: the adjoint is of the symplectic Euler step, not Verlet");
     const int64_t n = sim->d.n;
     RolloutBuffers& R = sim->ro;
     HIP_TRY(hipSetDevice(sim->device));
@@ -1133,7 +1169,11 @@ extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_mas
     if (block_masses) *block_masses = sim->lay.block;
     if (batch) *batch = sim->d.batch;
     if (persistent_groups) *persistent_groups = sim->d.persistent_groups;
-    if (step_form) *step_form = sim->d.sp_rec ? CRONOS_FORM_SPLIT : sim->d.packed ? CRONOS_FORM_TABLE : CRONOS_FORM_EXPLICIT;
+    if (step_form)
+        *step_form = sim->d.resident ? CRONOS_FORM_RESIDENT
+                     : sim->d.sp_rec ? CRONOS_FORM_SPLIT
+                     : sim->d.packed ? CRONOS_FORM_TABLE
+                                     : CRONOS_FORM_EXPLICIT;
     return CRONOS_OK;
 }
 

@@ -353,3 +353,44 @@ def test_layout_of_created_sim_matches_oracle():
     ora = LY.reorder(lat.ends, lat.body_offset, coords=lat.coords)
     for f in ("perm", "row_ptr", "col", "sid", "spring_perm"):
         assert np.array_equal(got[f], getattr(ora, f))
+
+
+# ------------------------------------------------------------------------- resident form
+
+def test_resident_form_bitwise_equal_to_table_form():
+    """A system of <= 1024 masses in one workgroup, many steps per launch: bitwise the same
+    states as the per-step launches (the same gather and update; factors by the same formula),
+    for the cube drop (contact, damping) and a small actuated robot, with both integrators."""
+    cube = W.cube_drop()
+    robot = W.population(1, lo=400, hi=900, first_robot=5)
+    say("case: resident form vs per-step launches: cube drop 1200 steps, one robot 700 steps")
+    for w, steps in ((cube, 1200), (robot, 700)):
+        for integ in (0, CR.VERLET):
+            ref, _, _ = PR.create(w, flags=integ)
+            res, _, _ = PR.create(w, flags=integ | CR.RESIDENT)
+            assert CR.cronos_launch_config(res)["step_form"] == "resident"
+            assert CR.cronos_launch_config(ref)["step_form"] == "table"
+            for chunk in (1, 99, steps - 100):
+                CR.cronos_step(ref, chunk)
+                CR.cronos_step(res, chunk)
+                a, b = CR.cronos_read_state(ref), CR.cronos_read_state(res)
+                assert a[2] == b[2]
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            da, db = CR.cronos_diagnostics(ref)[0], CR.cronos_diagnostics(res)[0]
+            assert da["ke"] == db["ke"] and np.array_equal(da["com"], db["com"])
+            ref.close()
+            res.close()
+
+
+def test_resident_form_matches_oracle_cube_1000():
+    w = W.cube_drop()
+    say("case: resident cube drop, steps 0-1000 vs oracle")
+    worst, sim, *_ = _run_pair(w, 1000, flags=CR.RESIDENT)
+    assert CR.cronos_launch_config(sim)["step_form"] == "resident"
+    say(f"  position err {worst:.3e}")
+    assert worst <= X_TOL
+
+
+def test_resident_flag_ignored_for_large_systems():
+    sim, _, _ = PR.create(W.cantilever(40, 8, 8), flags=CR.RESIDENT)
+    assert CR.cronos_launch_config(sim)["step_form"] == "table"

@@ -424,3 +424,71 @@ def test_actuated_rest_length_formula_and_period():
     np.testing.assert_allclose(P.rest_lengths(sys, 0.1), P.rest_lengths(sys, 0.6), rtol=1e-12)
     passive = sys.gidx < 0
     assert (P.rest_lengths(sys, 0.3)[passive] == sys.rest[passive]).all()
+
+
+# ---------------------------------------------------------------- Verlet (eqs. (5)-(6))
+
+@pytest.mark.parametrize("anchored", [False, True])
+def test_verlet_two_mass_exact_discrete_trajectory(anchored):
+    """Eq. (6) on the linear 1-D oscillator is u_{n+1} = (2 - w^2 dt^2) u_n - u_{n-1}, and eq. (5)
+    from rest gives u_1 = u0 (1 - w^2 dt^2 / 2) = u0 cos th: so u_n = u0 cos(n th) exactly,
+    cos th = 1 - w^2 dt^2 / 2 (Chebyshev recurrence)."""
+    k, m, l0, u0, dt = 50.0, 0.2, 0.1, 1e-3, 1e-3
+    sys, x0, v0 = _two_mass(k, m, l0, u0, dt, anchored)
+    w2 = (k / m) if anchored else (2 * k / m)
+    th = math.acos(1 - w2 * dt * dt / 2)
+    x_prev, x = x0, P.verlet_start(sys, x0, v0)
+    for n in range(1, 3001):
+        # the position form carries u in coordinates of ~0.1 m: rounding of 2 x_n - x_{n-1}
+        # accumulates to ~1e-14 over the run
+        u = x[1, 0] - x[0, 0] - l0
+        assert abs(u - u0 * math.cos(n * th)) <= 1e-10 * u0
+        x_prev, x = x, P.verlet_step(sys, x_prev, x, n)
+
+
+def test_verlet_free_fall_is_exact():
+    """Constant acceleration: eqs. (5)-(6) reproduce x0 + v0 t + g t^2 / 2 at every step."""
+    g, dt = np.array([0.0, 0.0, -9.81]), 1e-3
+    sys = P.System(mass=np.array([0.3]), pinned=np.array([False]), ends=np.zeros((0, 2), np.int64),
+                   k=np.zeros(0), rest=np.zeros(0), gidx=np.zeros(0, np.int64), gravity=g, damping=0.0, dt=dt)
+    x0, v0 = np.array([[0.1, -0.2, 1.0]]), np.array([[0.5, 0.25, 3.0]])
+    x, x_prev = P.run_verlet(sys, x0, v0, 0, 1000)
+    # rounding of 2 x_n - x_{n-1} acts as a velocity error, so it grows like n^2 ulp (~1e-10)
+    t = 1000 * dt
+    np.testing.assert_allclose(x, x0 + v0 * t + 0.5 * g * t * t, rtol=0, atol=1e-9)
+    t = 999 * dt
+    np.testing.assert_allclose(x_prev, x0 + v0 * t + 0.5 * g * t * t, rtol=0, atol=1e-9)
+
+
+def test_verlet_is_symplectic_euler_with_a_half_kick():
+    """Without contact and damping, eq. (6) is the symplectic Euler recurrence for the
+    positions; they coincide when Euler starts from v0 - dt/2 f(x0)/m (the first half kick of
+    eq. (5)).  Jittered cube with gravity, 300 steps."""
+    w = W.cube_drop(4)
+    lat = L.build(w)
+    sys = P.system_from(lat, w, ground=False, damping=0.0)
+    rng = np.random.default_rng(11)
+    x0 = lat.x + rng.uniform(-2e-4, 2e-4, lat.x.shape)
+    v0 = rng.normal(0.0, 0.01, lat.x.shape)
+    xv, _ = P.run_verlet(sys, x0, v0, 0, 300)
+    ve = v0 - 0.5 * sys.dt * P.forces(sys, x0, 0.0) / sys.mass[:, None]
+    xe, _ = P.run(sys, x0, ve, 0, 300)
+    np.testing.assert_allclose(xv, xe, rtol=0, atol=1e-12)
+
+
+def test_verlet_contact_and_damping_reading():
+    """With the contact plane and damping the Verlet step acts on the interval velocity
+    w = (x_{n+1} - x_n)/dt exactly as the Euler step acts on v (kick dt/2 in the first step):
+    a mass resting on the plane settles at the same penetration m g / k_g, and one sliding at
+    the equilibrium penetration loses mu g dt of speed per step."""
+    m, kg, mu, dt = 0.1, 1e5, 0.5, 1e-4
+    sys, x, v = _one_mass(0.0, m=m, kg=kg, d=0.01)
+    x, _ = P.run_verlet(sys, x, v, 0, 5000)
+    assert -x[0, 2] == pytest.approx(m * 9.81 / kg, rel=1e-6)
+    p_eq = m * 9.81 / kg
+    sys, x0, v0 = _one_mass(-p_eq, vx=0.2, m=m, kg=kg, mu=mu, dt=dt)
+    x_prev, x = x0, P.verlet_start(sys, x0, v0)
+    assert (x[0, 0] - x0[0, 0]) / dt == pytest.approx(0.2 - 0.5 * mu * 9.81 * dt, rel=1e-9)
+    for n in range(1, 101):
+        x_prev, x = x, P.verlet_step(sys, x_prev, x, n)
+    assert (x[0, 0] - x_prev[0, 0]) / dt == pytest.approx(0.2 - 100.5 * mu * 9.81 * dt, rel=1e-6)
