@@ -376,8 +376,10 @@ def test_resident_form_bitwise_equal_to_table_form():
                 a, b = CR.cronos_read_state(ref), CR.cronos_read_state(res)
                 assert a[2] == b[2]
                 assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            # the same state; the FP64 reductions group masses by workgroup, so only to rounding
             da, db = CR.cronos_diagnostics(ref)[0], CR.cronos_diagnostics(res)[0]
-            assert da["ke"] == db["ke"] and np.array_equal(da["com"], db["com"])
+            assert da["ke"] == pytest.approx(db["ke"], rel=1e-12)
+            np.testing.assert_allclose(da["com"], db["com"], rtol=1e-12)
             ref.close()
             res.close()
 
