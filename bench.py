@@ -261,8 +261,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
-    ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "surrogate", "adjoint"),
-                    default="cantilever")
+    ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "candidate", "surrogate",
+                                           "adjoint"), default="cantilever")
+    ap.add_argument("--points", type=int, default=200_000, help="candidate: points of the best-candidate bar")
     ap.add_argument("--resident", action="store_true", help="one-workgroup multi-step form (systems of <= 1024 masses)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint: rollout length")
     ap.add_argument("--pool", type=int, default=1024, help="surrogate: robots per morphology pool")
@@ -299,26 +300,30 @@ def main(argv=None):
     from paper_2207_09334_amd import cronos as CR
     from paper_2207_09334_amd import problem as PR
 
-    if args.workload == "population":
-        w = W.population(args.robots)
-    elif args.workload == "quadruped":
-        w = W.quadruped()
-    elif args.workload == "cube":
-        w = W.cube_drop()
-    else:
-        w = W.cantilever(args.nx, 40, 40)
-    lat = PR.build_lattice(w)
     stream = torch.cuda.Stream()
     flags = ((CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0) |
              (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0) |
              (CR.VERLET if args.integrator == "verlet" else 0) | (CR.RESIDENT if args.resident else 0))
-    sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block, batch=args.batch,
-                          tune_steps=20 if args.tune else 0)
+    if args.workload == "candidate":
+        w = W.candidate_bar(args.points)
+        sim, *_ = PR.create_points(w, stream=stream.cuda_stream, flags=flags, block_masses=args.block)
+        n_bodies, batched, actuated, lat = 1, False, False, None
+    else:
+        if args.workload == "population":
+            w = W.population(args.robots)
+        elif args.workload == "quadruped":
+            w = W.quadruped()
+        elif args.workload == "cube":
+            w = W.cube_drop()
+        else:
+            w = W.cantilever(args.nx, 40, 40)
+        lat = PR.build_lattice(w)
+        sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
+                              batch=args.batch, tune_steps=20 if args.tune else 0)
+        n_bodies, batched, actuated = len(w.bodies), len(w.bodies) > 1, w.n_groups > 0
     info = CR.cronos_info(sim)
     launch = CR.cronos_launch_config(sim)
     N, S = info["n_masses"], info["n_springs"]
-    batched = len(w.bodies) > 1
-    actuated = w.n_groups > 0
 
     copy_gbs = None
     if args.calibrate_copy:
@@ -367,7 +372,7 @@ def main(argv=None):
         "metric": METRIC, "value": value, "unit": "spring-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "n_bodies": len(w.bodies), "n_masses": N, "n_springs": S, "dt": w.dt,
+        "config": {"workload": w.name, "n_bodies": n_bodies, "n_masses": N, "n_springs": S, "dt": w.dt,
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
                    "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
                    "exact_difference": not args.fast_diff, "step_form": launch["step_form"],
@@ -389,7 +394,7 @@ def main(argv=None):
         out["rollouts_per_s"] = len(w.bodies) / (w.steps * sec_per_step)
         out["rollout_steps"] = w.steps
     sim.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and lat is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -135,6 +135,24 @@ void cronos_lattice_destroy(cronos_lattice lat);
  * input index).  Springs are renumbered by (min, max) of their new endpoints; the CSR row
  * of mass i lists (neighbour, spring) by increasing neighbour.  Host-only.
  * ---------------------------------------------------------------------------------------- */
+/* Quasi-uniform lattice points by best-candidate sampling (section "Generating a Lattice":
+ * Mitchell's best candidate, k nearest neighbours) in the box [0, size[0]) x [0, size[1]) x
+ * [0, size[2]).  Point 0 is a uniform draw; point p > 0 is, of n_candidates uniform draws, the
+ * one with the largest sum of distances to its min(k_nn, p) nearest placed points (distances
+ * summed in ascending order; ties keep the lowest candidate index).  Draws: coordinate a of
+ * candidate c of point p is size[a] * u, u = top 53 bits of h(seed, 8, p, c, a) * 2^-53, with
+ * h the SplitMix64 chain h(s, k0, k1, ...) = m(...m(m(m(s) ^ k0) ^ k1)...), m the SplitMix64
+ * output function (Steele, Lea & Flood 2014).  points: [n_points][3], caller-owned.
+ * Errors: EINVAL (sizes, n_candidates < 1, k_nn outside [1, 64]), ENOMEM. */
+cronos_status cronos_candidate_points(const double* size, int64_t n_points, int32_t n_candidates, int32_t k_nn,
+                                      uint64_t seed, double* points);
+/* Springs between every pair of points no farther apart than `cutoff` (d^2 = dx^2 + dy^2 + dz^2
+ * <= cutoff^2), as ends [S][2] with i < j, sorted by (i, j).  *n_springs receives S; ends is
+ * written when max_springs >= S (call with max_springs = 0 to count).  Errors: EINVAL
+ * (arguments, non-finite points, S > max_springs > 0), ENOMEM. */
+cronos_status cronos_cutoff_springs(int64_t n_points, const double* points, double cutoff, int64_t max_springs,
+                                    int32_t* ends, int64_t* n_springs);
+
 typedef struct cronos_layout_t* cronos_layout;
 
 /* x: [N][3] positions (used when grid is NULL); grid: [N][3] integer coordinates or NULL;

@@ -98,6 +98,8 @@ _SIGS = {
     "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
                               C.POINTER(_i64)]),
     "cronos_get_layout": (C.c_int, [_p] * 6),
+    "cronos_candidate_points": (C.c_int, [_p, _i64, _i32, _i32, C.c_uint64, _p]),
+    "cronos_cutoff_springs": (C.c_int, [_i64, _p, _f64, _i64, _p, C.POINTER(_i64)]),
     "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
     "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
@@ -280,6 +282,23 @@ def cronos_autotune(x0, mass, ends, k, rest, n_steps=20, **kw) -> dict:
 
 
 FORMS = ("explicit", "table", "split", "resident")
+
+
+def cronos_candidate_points(size, n_points: int, n_candidates: int = 100, k_nn: int = 4, seed: int = 0) -> np.ndarray:
+    sz = _arr(size, np.float64)
+    out = np.empty((int(n_points), 3))
+    _check(_lib.cronos_candidate_points(_ptr(sz), int(n_points), int(n_candidates), int(k_nn), C.c_uint64(seed),
+                                        _ptr(out)))
+    return out
+
+
+def cronos_cutoff_springs(points, cutoff: float) -> np.ndarray:
+    pts = _arr(points, np.float64, (-1, 3))
+    count = _i64()
+    _check(_lib.cronos_cutoff_springs(len(pts), _ptr(pts), float(cutoff), 0, None, C.byref(count)))
+    ends = np.empty((count.value, 2), np.int32)
+    _check(_lib.cronos_cutoff_springs(len(pts), _ptr(pts), float(cutoff), len(ends), _ptr(ends), C.byref(count)))
+    return ends
 
 
 def cronos_launch_config(sim: Sim) -> dict:

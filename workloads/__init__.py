@@ -39,6 +39,7 @@ S_AMP = 4
 S_WALK = 5
 S_SIZE = 6
 S_STATE = 7
+S_CANDIDATE = 8
 
 
 def _splitmix64(x):
@@ -347,3 +348,45 @@ def population_actuation(seed: int, n_robots: int, n_groups: int = 32, draw: int
     ph = 2.0 * math.pi * uniform01(seed, S_PHASE, draw, r, g)
     am = 0.25 * uniform01(seed, S_AMP, draw, r, g)
     return ph.ravel(), am.ravel()
+
+
+# ----------------------------------------------------------------------------------------
+# best-candidate point lattices (section "Generating a Lattice", second method)
+# ----------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PointWorkload:
+    """A quasi-uniform lattice grown by best-candidate sampling in a box: the sampling
+    parameters (candidate coordinates are uniform01(seed, S_CANDIDATE, point, candidate, axis)
+    times the box size), the spring cutoff, and the physical constants.  Springs get
+    k = k_ref * length_ref / length (the paper's default spring constant, scaled inversely to
+    the spring's length) and rest length = initial length; every point has the same mass."""
+    name: str
+    size: tuple
+    n_points: int
+    n_candidates: int
+    k_nn: int
+    seed: int
+    cutoff: float
+    k_ref: float
+    length_ref: float
+    mass: float
+    pin_x: float            # points with x < pin_x are fixed (the x = 0 end of the bar)
+    gravity: tuple
+    damping: float
+    dt: float
+    ground: bool = False
+    ground_z: float = 0.0
+    ground_k: float = 0.0
+    ground_mu: float = 0.0
+    steps: int = 1000
+
+
+def candidate_bar(n_points: int = 200_000, size=(0.4, 0.04, 0.04), seed: int = 5) -> PointWorkload:
+    """A bar of best-candidate points (100 candidates, nearest-neighbour criterion), springs up
+    to 1.6 mean spacings, 0.1 kg per point, k = 1e4 N/m at the mean spacing, fixed at x = 0,
+    sagging under gravity."""
+    spacing = (size[0] * size[1] * size[2] / n_points) ** (1.0 / 3.0)
+    return PointWorkload(name=f"candidate_bar_{n_points}", size=tuple(size), n_points=n_points, n_candidates=100,
+                         k_nn=1, seed=seed, cutoff=1.6 * spacing, k_ref=1.0e4, length_ref=spacing, mass=0.1,
+                         pin_x=0.75 * spacing, gravity=(0.0, 0.0, -9.81), damping=0.0, dt=1.0e-4)
