@@ -65,3 +65,15 @@ def test_bench_refuses_more_than_one_gpu(capsys):
         bench.main(["--gpus", "2"])
     assert e.value.code != 0
     assert "one GPU" in capsys.readouterr().err
+
+
+@pytest.mark.parametrize("f_true", [0.2503, 1.0062, 3.7])
+def test_spectral_peak_recovers_a_known_frequency(f_true):
+    """The frequency tool's FFT peak: a decaying-free sinusoid over ~6 periods with an offset,
+    a weaker second harmonic and noise, sampled 200 times per period."""
+    h = 1.0 / f_true / 200.0
+    t = np.arange(1281) * h
+    rng = np.random.default_rng(11)
+    z = (0.0973 + 4e-4 * np.cos(2 * np.pi * f_true * t + 0.3) + 3e-5 * np.sin(4 * np.pi * f_true * t)
+         + 2e-6 * rng.standard_normal(t.size))
+    assert bench.spectral_peak(z, h) == pytest.approx(f_true, rel=2e-3)
