@@ -203,6 +203,46 @@ def frequency_bench(args) -> dict:
             "beams": rows, "sim_seconds": t_sim, "steps": steps_total}
 
 
+def modes_bench(args) -> dict:
+    """Natural frequencies by the device's Lanczos solver (section "Natural Frequency
+    Analysis": the generalised eigenproblem of the linearised system) for the cantilevers of
+    the frequency sweep at rest: the two lowest distinct frequencies, the Lanczos steps they
+    took and the time, with the first compared with Euler-Bernoulli."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2207_09334_amd import cronos as CR
+    from paper_2207_09334_amd import problem as PR
+
+    K1, E, rho, a = 1.8751040687, 1.0e6, 1000.0, 0.005
+    rows, t_all = [], 0.0
+    for nx, ny, nz in args.sweep:
+        w = W.cantilever(nx, ny, nz, youngs=E, spacing=a)
+        Lb, Wd, H = (nx - 1) * a, (ny - 1) * a, (nz - 1) * a
+        f_eb = K1 ** 2 / (2 * math.pi) * math.sqrt(E * (Wd * H ** 3 / 12.0) / (rho * Wd * H * Lb ** 4))
+        stream = torch.cuda.Stream()
+        sim, _, _ = PR.create(w, stream=stream.cuda_stream, gravity=(0.0, 0.0, 0.0))
+        t0 = time.perf_counter()
+        om, iters = CR.cronos_natural_frequencies(sim, n_modes=2, max_iter=args.modes_iter, tol=1e-9)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        info = CR.cronos_info(sim)
+        f = [float(o / (2 * math.pi)) for o in om]
+        rows.append({"nodes": [nx, ny, nz], "masses": info["n_masses"], "springs": info["n_springs"],
+                     "f_hz": f, "f_euler_bernoulli_hz": f_eb, "ratio": f[0] / f_eb if f else None,
+                     "lanczos_steps": iters, "seconds": dt, "us_per_step": 1e6 * dt / max(iters, 1)})
+        sim.close()
+        print(f"modes: {nx}x{ny}x{nz} f {f} Hz (EB {f_eb:.4f}), {iters} steps, {dt:.2f} s", file=sys.stderr,
+              flush=True)
+    return {"metric": "Lanczos first frequency / Euler-Bernoulli", "value": float(np.mean([r["ratio"] for r in rows if r["ratio"]])),
+            "unit": "ratio", "higher_is_better": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "cantilever_modes", "youngs": E, "density": rho, "spacing": a},
+            "beams": rows, "seconds": t_all}
+
+
 def spectral_peak(z, h: float) -> float:
     """Frequency (Hz) of the strongest component of samples z taken every h seconds: mean
     removed, Hann window, zero-padded FFT, peak refined by a parabola through the log
@@ -333,10 +373,11 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
     ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "candidate", "surrogate",
-                                           "adjoint", "frequency"), default="cantilever")
+                                           "adjoint", "frequency", "modes"), default="cantilever")
     ap.add_argument("--sweep", type=lambda t: [tuple(int(v) for v in b.split("x")) for b in t.split(",")],
                     default=[(200, 40, 40), (300, 40, 40), (400, 40, 40), (400, 40, 30), (400, 40, 20), (400, 20, 40)],
-                    help="frequency: beams as NXxNYxNZ node counts, comma separated")
+                    help="frequency, modes: beams as NXxNYxNZ node counts, comma separated")
+    ap.add_argument("--modes-iter", type=int, default=1_000_000, help="modes: Lanczos step cap per beam")
     ap.add_argument("--points", type=int, default=200_000, help="candidate: points of the best-candidate bar")
     ap.add_argument("--resident", action="store_true", help="one-workgroup multi-step form (systems of <= 1024 masses)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint: rollout length")
@@ -371,6 +412,9 @@ def main(argv=None):
         return
     if args.workload == "frequency":
         print(json.dumps(frequency_bench(args)), flush=True)
+        return
+    if args.workload == "modes":
+        print(json.dumps(modes_bench(args)), flush=True)
         return
 
     import workloads as W

@@ -260,6 +260,34 @@ cronos_status cronos_set_state(cronos_sim sim, const double* x, const double* v,
  * and t_n (input order, [N][3]), evaluated by the same gather as the step.  Blocking. */
 cronos_status cronos_eval_forces(cronos_sim sim, double* f);
 
+/* Lowest natural frequencies of the system linearised about its current positions (section
+   "Natural Frequency Analysis": the generalised eigenproblem K v = w^2 M v, K the tangent
+   stiffness of the springs of eq. (2) -- k [n n^T + (1 - l0/l)(I - n n^T)] per spring, rest
+   lengths times the current actuation factors -- plus k_g on z for masses below the contact
+   plane, M the diagonal masses, fixed masses removed).  Lanczos iterations on M^-1/2 K M^-1/2
+   run on the device in FP64 (no reorthogonalisation; repeated Ritz values are merged), the
+   host takes the smallest eigenvalues of the tridiagonal matrix by bisection and stops when
+   the first n_modes are within tol: error bound min(r, r^2/gap) with r the Lanczos residual,
+   relative to w^2, never below ~1e-15 times the largest w^2 (what FP64 resolves).
+   n_modes in [1, 32] distinct frequencies; max_iter in [2 n_modes + 8, 2^24] caps the Lanczos
+   steps; seed picks the random start vector.  omega[n_modes] receives the angular
+   frequencies (rad/s) in increasing order (a negative value -sqrt(-w^2) marks an unstable
+   direction; entries beyond *n_found are 0); *n_found the number that converged;
+   *iterations (may be NULL) the steps taken.  Multiplicity is not resolved: an eigenvalue of
+   multiplicity m (a square beam's two bending modes) is reported once.  Allocates about
+   80 bytes per mass of device memory for the call; the simulation state is not changed.  EINVAL for bad arguments, ENOMEM, ESTATE if the iteration breaks down. */
+cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
+                                         uint64_t seed, double* omega, int32_t* n_found, int32_t* iterations);
+
+/* The host step of cronos_natural_frequencies, exposed so it can be checked on its own: the
+   `count` smallest eigenvalues theta[count] (increasing) of the symmetric tridiagonal matrix
+   with diagonal a[k] and off-diagonal b[k-1] (NULL allowed when k = 1), by Sturm-sequence
+   bisection, and (if last != NULL) the magnitude of the last entry of each one's unit
+   eigenvector, by two steps of inverse iteration.  Host memory only.  EINVAL when
+   count is outside [1, k] or an entry is not finite. */
+cronos_status cronos_tridiag_smallest(int64_t k, const double* a, const double* b, int64_t count, double* theta,
+                                      double* last);
+
 /* Diagnostics of every body at the current state (out: [n_bodies]).  Blocking.
  * Returns ESTATE (after filling out) when some body holds a non-finite value. */
 cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);

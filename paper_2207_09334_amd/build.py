@@ -19,7 +19,8 @@ LIB = os.path.join(PKG, "libcronos.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["lattice.cpp", "layout.cpp", "sim.cpp", "kernels.hip", "mlp.hip", "features.cpp", "candidate.cpp"]
+SOURCES = ["lattice.cpp", "layout.cpp", "sim.cpp", "kernels.hip", "mlp.hip", "features.cpp", "candidate.cpp",
+           "modes.hip", "tridiag.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result",
           f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -95,6 +95,9 @@ _SIGS = {
     "cronos_set_state": (C.c_int, [_p, _p, _p, _i64]),
     "cronos_eval_forces": (C.c_int, [_p, _p]),
     "cronos_diagnostics": (C.c_int, [_p, C.POINTER(Diag)]),
+    "cronos_natural_frequencies": (C.c_int, [_p, _i32, _i32, _f64, C.c_uint64, _p, C.POINTER(_i32),
+                                             C.POINTER(_i32)]),
+    "cronos_tridiag_smallest": (C.c_int, [_i64, _p, _p, _i64, _p, _p]),
     "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
                               C.POINTER(_i64)]),
     "cronos_get_layout": (C.c_int, [_p] * 6),
@@ -342,6 +345,28 @@ def cronos_eval_forces(sim: Sim) -> np.ndarray:
     f = np.empty((sim.n_masses, 3))
     _check(_lib.cronos_eval_forces(sim.handle, _ptr(f)))
     return f
+
+
+def cronos_natural_frequencies(sim: Sim, n_modes: int = 2, max_iter: int = 200_000, tol: float = 1e-9,
+                               seed: int = 1) -> tuple:
+    """Lowest distinct angular frequencies (rad/s) of the system linearised about its current
+    positions; returns (omega[:n_found], iterations)."""
+    omega = np.zeros(n_modes)
+    found, iters = _i32(0), _i32(0)
+    _check(_lib.cronos_natural_frequencies(sim.handle, n_modes, max_iter, tol, seed, _ptr(omega), C.byref(found),
+                                           C.byref(iters)))
+    return omega[:found.value].copy(), iters.value
+
+
+def cronos_tridiag_smallest(a, b, count: int) -> tuple:
+    """Smallest `count` eigenvalues of the symmetric tridiagonal matrix (diagonal a,
+    off-diagonal b) and |last entry| of their unit eigenvectors."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    theta, last = np.empty(count), np.empty(count)
+    _check(_lib.cronos_tridiag_smallest(len(a), _ptr(a), _ptr(b) if len(b) else None, count, _ptr(theta),
+                                        _ptr(last)))
+    return theta, last
 
 
 def cronos_diagnostics(sim: Sim, allow_nonfinite=False) -> list:

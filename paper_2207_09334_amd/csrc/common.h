@@ -37,6 +37,16 @@ void parallel_for(int64_t n, F fn, int64_t min_chunk = 1024) {
 cronos_status fail(cronos_status st, const char* fmt, ...);
 void clear_error();
 
+// Symmetric tridiagonal eigenvalues (tridiag.cpp): T has diagonal a[0..k) and off-diagonal
+// b[0..k-1) (b2 = squares).  sturm_count = eigenvalues below x; tridiag_eigenvalue = the
+// index-th smallest by bisection in [lo, hi]; eigvec_last_component = |last entry| of the
+// unit eigenvector for an eigenvalue approximation theta (inverse iteration).
+int64_t sturm_count(const double* a, const double* b2, int64_t k, double x, double tiny);
+void gershgorin(const double* a, const double* b, int64_t k, double* lo, double* hi);
+double tridiag_eigenvalue(const double* a, const double* b2, int64_t k, int64_t index, double lo, double hi,
+                          double tiny);
+double eigvec_last_component(const double* a, const double* b, int64_t k, double theta, double tiny);
+
 // Masses per 64-lane slice: one wavefront owns one slice, one lane per mass.
 constexpr int kSlice = 64;
 // Default masses per workgroup (4 wavefronts).

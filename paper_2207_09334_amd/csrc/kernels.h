@@ -97,6 +97,22 @@ hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float*
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
                              double2* sens, double cos_t, double sin_t, hipStream_t st);
 hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
+
+// Lanczos iterations for the natural frequencies (modes.hip), FP64.
+struct ModesBuffers {
+    double* ism = nullptr;               // [n] M^-1/2 (0 for fixed masses)
+    double* q[2] = {nullptr, nullptr};   // [3n] Lanczos vectors, alternating roles
+    double* y = nullptr;                 // [3n] A q
+    double* part_a = nullptr;            // [nblk] partial q . A q
+    double* part_u = nullptr;            // [ceil(n / 256)] partial squared norms
+    double* alpha = nullptr;             // [max_iter] diagonal of the tridiagonal matrix
+    double* beta = nullptr;              // [max_iter] off-diagonal (beta[k] follows step k)
+};
+// Random start vector q_0 (normalised, in q[1]; q[0] must hold zeros) and M^-1/2.
+hipError_t launch_modes_init(const DeviceArrays& d, int cur, ModesBuffers& m, unsigned long long seed, hipStream_t st);
+// Lanczos step k: alpha[k], beta[k] and q_{k+1} from q_k and q_{k-1}.
+hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepParams& p, ModesBuffers& m, int k,
+                                  hipStream_t st);
 hipError_t launch_diagnostics(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 
 }  // namespace cronos

@@ -1,0 +1,210 @@
+// Natural frequencies of the linearised mass-spring system (section "Natural Frequency
+// Analysis": the generalised eigenproblem K v = w^2 M v).  Lanczos iterations on the
+// symmetric operator A = M^-1/2 K M^-1/2 run on the device in FP64; the host takes the
+// eigenvalues of the tridiagonal matrix they build (see cronos_natural_frequencies).
+//
+// K is the tangent stiffness of the Hookean springs of eq. (2) at the current positions:
+// for a spring with unit direction n, length l and (actuated) rest length l0 its 3x3 block is
+// k [n n^T + (1 - l0 / l)(I - n n^T)], entering the two diagonal blocks with + and the two
+// off-diagonal blocks with -, so that df = -K dx; a mass below the contact plane adds the
+// penalty stiffness k_g to its z diagonal.  Fixed masses are removed (their M^-1/2 is 0).
+//
+// Layout: the step's explicit incidence form (per-lane slices of (LDS slot, k, L0) with
+// halo indices), one workgroup per block of masses, neighbours read straight from global
+// memory (L2); every sum is reduced in a fixed order, so a run is bitwise repeatable.
+#include "kernels.h"
+
+namespace cronos {
+namespace {
+
+constexpr int kMaxWaves = 16;
+
+__device__ __forceinline__ double wave_add(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup: wavefront sums, then added in wavefront order by one lane.
+__device__ double workgroup_sum(double v, double* red) {
+    v = wave_add(v);
+    const int t = (int)threadIdx.x, nw = ((int)blockDim.x + 63) >> 6;
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w];
+        red[kMaxWaves] = s;
+    }
+    __syncthreads();
+    const double s = red[kMaxWaves];
+    __syncthreads();
+    return s;
+}
+
+// Sum of part[0..count) in a fixed order (the same in every workgroup).
+__device__ double sum_parts(const double* __restrict__ part, int count, double* red) {
+    double a = 0.0;
+    for (int q = (int)threadIdx.x; q < count; q += (int)blockDim.x) a += part[q];
+    return workgroup_sum(a, red);
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// M^-1/2 per mass and a random start vector (zero on fixed masses); partial squared norms.
+__global__ void __launch_bounds__(256) modes_init_kernel(const float4* __restrict__ x, const float* __restrict__ mass,
+                                                         double* __restrict__ ism, double* __restrict__ w,
+                                                         double* __restrict__ part, int n, unsigned long long seed) {
+    __shared__ double red[kMaxWaves + 1];
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    double nn = 0.0;
+    if (i < n) {
+        const bool free_mass = x[i].w != 0.0f;
+        ism[i] = free_mass ? 1.0 / sqrt((double)mass[i]) : 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const unsigned long long h = mix64(seed + 0x9e3779b97f4a7c15ull * (unsigned long long)(3 * (long long)i + c + 1));
+            const double u = free_mass ? (double)(h >> 11) * 0x1.0p-53 - 0.5 : 0.0;
+            w[3 * i + c] = u;
+            nn += u * u;
+        }
+    }
+    const double s = workgroup_sum(nn, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+struct ApplyArgs {
+    const float4* __restrict__ x;
+    const double* __restrict__ ism;
+    const int32_t* __restrict__ slice_ptr;
+    const uint16_t* __restrict__ nbr;
+    const float2* __restrict__ kl;
+    const uint16_t* __restrict__ grp;
+    const float* __restrict__ factor;
+    const int32_t* __restrict__ halo_ptr;
+    const int32_t* __restrict__ halo_idx;
+    const uint16_t* __restrict__ lane_mass;
+    int n, block;
+    int ground;
+    float ground_z, ground_k;
+};
+
+// y = A q for the masses of workgroup-block b, and the block's part of q . y.
+__global__ void __launch_bounds__(1024) modes_apply_kernel(ApplyArgs a, const double* __restrict__ q,
+                                                           double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double red[kMaxWaves + 1];
+    const int b = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int base = b * a.block;
+    const int i = base + a.lane_mass[base + t];
+    double dot = 0.0;
+    if (i < a.n) {
+        const float4 xi = a.x[i];
+        const double si = a.ism[i];
+        const double u0 = si * q[3 * i], u1 = si * q[3 * i + 1], u2 = si * q[3 * i + 2];
+        double k0 = 0.0, k1 = 0.0, k2 = 0.0;
+        const int s = (base + t) >> 6, lane = t & 63;
+        const int e0 = a.slice_ptr[s];
+        const int width = (a.slice_ptr[s + 1] - e0) >> 6;
+        const int h0 = a.halo_ptr[b];
+        for (int r = 0, e = e0 + lane; r < width; ++r, e += 64) {
+            const int slot = a.nbr[e];
+            const int j = slot < a.block ? base + slot : a.halo_idx[h0 + slot - a.block];
+            if (j == i) continue;  // padding
+            const float2 c = a.kl[e];
+            double l0 = (double)c.y;
+            if (a.grp) l0 *= (double)a.factor[a.grp[e]];
+            const float4 xj = a.x[j];
+            const double dx = (double)xj.x - (double)xi.x, dy = (double)xj.y - (double)xi.y,
+                         dz = (double)xj.z - (double)xi.z;
+            const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+            const double nx = dx * il, ny = dy * il, nz = dz * il;
+            const double sj = a.ism[j];
+            const double d0 = u0 - sj * q[3 * j], d1 = u1 - sj * q[3 * j + 1], d2 = u2 - sj * q[3 * j + 2];
+            const double nd = nx * d0 + ny * d1 + nz * d2;
+            const double g = 1.0 - l0 * il;
+            const double kk = (double)c.x;
+            k0 += kk * (nd * nx + g * (d0 - nd * nx));
+            k1 += kk * (nd * ny + g * (d1 - nd * ny));
+            k2 += kk * (nd * nz + g * (d2 - nd * nz));
+        }
+        if (a.ground && xi.z < a.ground_z) k2 += (double)a.ground_k * u2;
+        const double y0 = si * k0, y1 = si * k1, y2 = si * k2;
+        y[3 * i] = y0;
+        y[3 * i + 1] = y1;
+        y[3 * i + 2] = y2;
+        dot = q[3 * i] * y0 + q[3 * i + 1] * y1 + q[3 * i + 2] * y2;
+    }
+    const double sum = workgroup_sum(dot, red);
+    if (t == 0) part[b] = sum;
+}
+
+// alpha_k = q . y (from the apply kernel's parts); w = y - alpha_k q - beta_k q_prev written
+// over q_prev; partial squared norms of w.
+__global__ void __launch_bounds__(256) modes_update_kernel(const double* __restrict__ apart, int n_apart,
+                                                           const double* __restrict__ y, const double* __restrict__ q,
+                                                           double* __restrict__ qw, double* __restrict__ alpha,
+                                                           const double* __restrict__ beta, int k,
+                                                           double* __restrict__ part, int n) {
+    __shared__ double red[kMaxWaves + 1];
+    const double al = sum_parts(apart, n_apart, red);
+    const double bp = k > 0 ? beta[k - 1] : 0.0;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    double nn = 0.0;
+    if (i < n) {
+        for (int c = 0; c < 3; ++c) {
+            const double w = y[3 * i + c] - al * q[3 * i + c] - bp * qw[3 * i + c];
+            qw[3 * i + c] = w;
+            nn += w * w;
+        }
+    }
+    const double s = workgroup_sum(nn, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[k] = al;
+}
+
+// beta = |w| (from the parts); w /= beta in place; beta stored at beta[k] when k >= 0.
+__global__ void __launch_bounds__(256) modes_scale_kernel(const double* __restrict__ part, int n_part,
+                                                          double* __restrict__ w, double* __restrict__ beta, int k,
+                                                          int n) {
+    __shared__ double red[kMaxWaves + 1];
+    const double b = sqrt(sum_parts(part, n_part, red));
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n)
+        for (int c = 0; c < 3; ++c) w[3 * i + c] *= inv;
+    if (k >= 0 && blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
+}
+
+}  // namespace
+
+hipError_t launch_modes_init(const DeviceArrays& d, int cur, ModesBuffers& m, unsigned long long seed, hipStream_t st) {
+    const int n = (int)d.n, g = (n + 255) / 256;
+    hipLaunchKernelGGL(modes_init_kernel, dim3(g), dim3(256), 0, st, d.x[cur], d.mass, m.ism, m.q[1], m.part_u, n,
+                       seed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(modes_scale_kernel, dim3(g), dim3(256), 0, st, m.part_u, g, m.q[1], m.beta, -1, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepParams& p, ModesBuffers& m, int k,
+                                  hipStream_t st) {
+    const int n = (int)d.n, g = (n + 255) / 256;
+    double* q = m.q[(k + 1) & 1];   // q_k (the start vector q_0 sits in q[1])
+    double* qw = m.q[k & 1];        // q_{k-1} in, q_{k+1} out
+    ApplyArgs a{d.x[cur], m.ism, d.slice_ptr, d.nbr, d.kl, d.grp, d.factor, d.halo_ptr, d.halo_idx, d.lane_mass,
+                n, d.block, p.ground, p.ground_z, p.ground_k};
+    hipLaunchKernelGGL(modes_apply_kernel, dim3((unsigned)d.nblk), dim3(d.block), 0, st, a, q, m.y, m.part_a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(modes_update_kernel, dim3(g), dim3(256), 0, st, m.part_a, (int)d.nblk, m.y, q, qw, m.alpha,
+                       m.beta, k, m.part_u, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(modes_scale_kernel, dim3(g), dim3(256), 0, st, m.part_u, g, qw, m.beta, k, n);
+    return hipGetLastError();
+}
+
+}  // namespace cronos

@@ -966,6 +966,135 @@ extern "C" cronos_status cronos_eval_forces(cronos_sim sim, double* f) {
     return CRONOS_OK;
 }
 
+namespace {
+
+// Ritz values of the Lanczos tridiagonal matrix T_k with their error estimates.  Values whose
+// residual intervals overlap are copies of one eigenvalue (the "ghosts" that plain Lanczos
+// produces once an eigenvalue has converged) and are merged, keeping the smallest residual.
+struct RitzCluster {
+    double theta, err, floor;  // floor: the error that FP64 arithmetic on T cannot go below
+};
+
+std::vector<RitzCluster> ritz_clusters(const std::vector<double>& a, const std::vector<double>& b, int64_t k,
+                                       int64_t count) {
+    std::vector<double> b2(k > 1 ? k - 1 : 1);
+    for (int64_t i = 0; i + 1 < k; ++i) b2[i] = b[i] * b[i];
+    double lo, hi;
+    cronos::gershgorin(a.data(), b.data(), k, &lo, &hi);
+    const double norm = std::max(std::fabs(lo), std::fabs(hi));
+    const double tiny_count = 1e-300, tiny_solve = 1e-15 * std::max(norm, 1e-300);
+    const double beta_k = b[k - 1];  // norm of the next Lanczos residual
+    std::vector<double> th(count), r(count);
+    double lower = lo;
+    for (int64_t j = 0; j < count; ++j) {
+        th[j] = cronos::tridiag_eigenvalue(a.data(), b2.data(), k, j, lower, hi, tiny_count);
+        lower = std::max(lo, th[j] - 4e-16 * norm);
+        r[j] = std::fabs(beta_k) * cronos::eigvec_last_component(a.data(), b.data(), k, th[j], tiny_solve);
+    }
+    std::vector<RitzCluster> out;
+    std::vector<double> out_r;
+    for (int64_t j = 0; j < count; ++j) {
+        if (!out.empty() && th[j] - out.back().theta <= r[j] + out_r.back() + 8e-16 * norm) {
+            if (r[j] < out_r.back()) {
+                out.back().theta = th[j];
+                out_r.back() = r[j];
+            }
+            continue;
+        }
+        out.push_back({th[j], 0.0, 0.0});
+        out_r.push_back(r[j]);
+    }
+    // error bound min(r, r^2 / gap), gap to the neighbouring clusters; never below what the
+    // FP64 arithmetic on T itself resolves
+    const double floor = 8e-16 * norm;
+    for (size_t c = 0; c < out.size(); ++c) {
+        double gap = 1e300;
+        if (c > 0) gap = std::min(gap, out[c].theta - out[c - 1].theta);
+        if (c + 1 < out.size()) gap = std::min(gap, out[c + 1].theta - out[c].theta);
+        const double rr = out_r[c];
+        out[c].err = std::max(std::min(rr, rr * rr / gap), floor);
+        out[c].floor = floor;
+    }
+    // the last cluster's upper neighbour is unknown: only its residual bounds it
+    if (!out.empty()) out.back().err = std::max(out_r.back(), floor);
+    return out;
+}
+
+}  // namespace
+
+extern "C" cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
+                                                    uint64_t seed, double* omega, int32_t* n_found,
+                                                    int32_t* iterations) {
+    cronos::clear_error();
+    if (!sim || !omega || !n_found) return fail(CRONOS_EINVAL, "natural_frequencies: NULL argument");
+    if (n_modes < 1 || n_modes > 32) return fail(CRONOS_EINVAL, "natural_frequencies: n_modes must be in [1, 32]");
+    if (max_iter < 2 * n_modes + 8 || max_iter > (1 << 24))
+        return fail(CRONOS_EINVAL, "natural_frequencies: max_iter must be in [2 n_modes + 8, 2^24]");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(CRONOS_EINVAL, "natural_frequencies: tol must be in (0, 1)");
+    const int64_t n = sim->d.n;
+    HIP_TRY(hipSetDevice(sim->device));
+    cronos::ModesBuffers m;
+    const int64_t nu = (n + 255) / 256;
+    std::vector<void*> owned;
+    auto alloc = [&](double** p, size_t count) -> cronos_status {
+        if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess)
+            return fail(CRONOS_ENOMEM, "natural_frequencies: device allocation of %zu doubles failed", count);
+        owned.push_back(*p);
+        return CRONOS_OK;
+    };
+    auto run = [&]() -> cronos_status {
+        TRY(alloc(&m.ism, n));
+        TRY(alloc(&m.q[0], 3 * n));
+        TRY(alloc(&m.q[1], 3 * n));
+        TRY(alloc(&m.y, 3 * n));
+        TRY(alloc(&m.part_a, sim->d.nblk));
+        TRY(alloc(&m.part_u, nu));
+        TRY(alloc(&m.alpha, max_iter));
+        TRY(alloc(&m.beta, max_iter));
+        HIP_TRY(hipMemsetAsync(m.q[0], 0, 3 * n * sizeof(double), sim->stream));
+        if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
+        HIP_TRY(cronos::launch_modes_init(sim->d, sim->cur, m, seed, sim->stream));
+        std::vector<double> ha(max_iter), hb(max_iter);
+        int32_t k = 0, next = std::min<int32_t>(max_iter, std::max<int32_t>(64, 4 * n_modes + 16));
+        int32_t found = 0;
+        std::vector<double> best;
+        while (true) {
+            for (; k < next; ++k) HIP_TRY(cronos::launch_modes_iteration(sim->d, sim->cur, sim->p, m, k, sim->stream));
+            HIP_TRY(hipMemcpyAsync(ha.data(), m.alpha, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+            HIP_TRY(hipMemcpyAsync(hb.data(), m.beta, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+            HIP_TRY(hipStreamSynchronize(sim->stream));
+            for (int32_t i = 0; i < k; ++i)
+                if (!std::isfinite(ha[i]) || !std::isfinite(hb[i]))
+                    return fail(CRONOS_ESTATE, "natural_frequencies: non-finite Lanczos coefficient at step %d", i);
+            const int64_t count = std::min<int64_t>(k, 2 * n_modes + 8);
+            std::vector<RitzCluster> cl = ritz_clusters(ha, hb, k, count);
+            // the converged prefix: every cluster up to it has an error within tol
+            int32_t conv = 0;
+            for (const RitzCluster& c : cl) {
+                if (c.err > tol * std::fabs(c.theta) && c.err > c.floor && !(hb[k - 1] == 0.0)) break;
+                ++conv;
+            }
+            found = std::min<int32_t>(conv, n_modes);
+            best.clear();
+            for (int32_t c = 0; c < found; ++c) best.push_back(cl[c].theta);
+            const bool exhausted = hb[k - 1] <= 1e-14 * std::fabs(ha[0]) || k >= std::min<int64_t>(max_iter, 3 * n);
+            if (found >= n_modes || exhausted || k >= max_iter) break;
+            next = (int32_t)std::min<int64_t>(max_iter, (int64_t)k + std::max<int64_t>(256, k / 4));
+        }
+        for (int32_t c = 0; c < n_modes; ++c) {
+            const double t = c < found ? best[c] : 0.0;
+            omega[c] = t >= 0.0 ? std::sqrt(t) : -std::sqrt(-t);
+        }
+        *n_found = found;
+        if (iterations) *iterations = k;
+        return CRONOS_OK;
+    };
+    const cronos_status st = run();
+    (void)hipStreamSynchronize(sim->stream);
+    for (void* p : owned) (void)hipFree(p);
+    return st;
+}
+
 extern "C" cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out) {
     cronos::clear_error();
     if (!sim || !out) return fail(CRONOS_EINVAL, "diagnostics: NULL argument");
