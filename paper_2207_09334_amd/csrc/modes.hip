@@ -10,14 +10,16 @@
 // penalty stiffness k_g to its z diagonal.  Fixed masses are removed (their M^-1/2 is 0).
 //
 // Layout: the step's explicit incidence form (per-lane slices of (LDS slot, k, L0) with
-// halo indices), one workgroup per block of masses, neighbours read straight from global
-// memory (L2); every sum is reduced in a fixed order, so a run is bitwise repeatable.
+// halo indices), one workgroup per block of masses whose positions and M^-1/2 q (with the
+// halo's) are staged in LDS first; every sum is reduced in a fixed order, so a run is
+// bitwise repeatable.
 #include "kernels.h"
 
 namespace cronos {
 namespace {
 
 constexpr int kMaxWaves = 16;
+constexpr size_t kModesMaxLds = 150 * 1024;   // dynamic LDS of the staged apply kernel (of 160 KiB)
 
 __device__ __forceinline__ double wave_add(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -86,12 +88,86 @@ struct ApplyArgs {
     const int32_t* __restrict__ halo_ptr;
     const int32_t* __restrict__ halo_idx;
     const uint16_t* __restrict__ lane_mass;
-    int n, block;
+    int n, block, lds_slots;
     int ground;
     float ground_z, ground_k;
 };
 
-// y = A q for the masses of workgroup-block b, and the block's part of q . y.
+// Contribution of spring (i, j) to (K u)_i: k [n n^T + (1 - l0/l)(I - n n^T)] (u_i - u_j).
+__device__ __forceinline__ void spring_hessian(float4 xi, float4 xj, double u0, double u1, double u2, double v0,
+                                               double v1, double v2, double kk, double l0, double& k0, double& k1,
+                                               double& k2) {
+    const double dx = (double)xj.x - (double)xi.x, dy = (double)xj.y - (double)xi.y, dz = (double)xj.z - (double)xi.z;
+    const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    const double nx = dx * il, ny = dy * il, nz = dz * il;
+    const double d0 = u0 - v0, d1 = u1 - v1, d2 = u2 - v2;
+    const double nd = nx * d0 + ny * d1 + nz * d2;
+    const double g = 1.0 - l0 * il;
+    k0 += kk * (nd * nx + g * (d0 - nd * nx));
+    k1 += kk * (nd * ny + g * (d1 - nd * ny));
+    k2 += kk * (nd * nz + g * (d2 - nd * nz));
+}
+
+// y = A q with the workgroup's masses and halo staged in LDS: positions (float4) and
+// u = M^-1/2 q (FP64) per slot, so the incidence loop reads no global memory but its entries.
+__global__ void __launch_bounds__(1024) modes_apply_lds_kernel(ApplyArgs a, const double* __restrict__ q,
+                                                               double* __restrict__ y, double* __restrict__ part) {
+    extern __shared__ float4 sx[];                       // [lds_slots] positions
+    double* su = reinterpret_cast<double*>(sx + a.lds_slots);   // [lds_slots][3] u
+    __shared__ double red[kMaxWaves + 1];
+    const int b = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int base = b * a.block;
+    const int h0 = a.halo_ptr[b], slots = a.block + (a.halo_ptr[b + 1] - h0);
+    for (int sl = t; sl < slots; sl += (int)blockDim.x) {
+        const int m = sl < a.block ? base + sl : a.halo_idx[h0 + sl - a.block];
+        float4 xm = make_float4(0.f, 0.f, 0.f, 0.f);
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+        if (m < a.n) {
+            xm = a.x[m];
+            const double sm = a.ism[m];
+            u0 = sm * q[3 * m];
+            u1 = sm * q[3 * m + 1];
+            u2 = sm * q[3 * m + 2];
+        }
+        sx[sl] = xm;
+        su[3 * sl] = u0;
+        su[3 * sl + 1] = u1;
+        su[3 * sl + 2] = u2;
+    }
+    __syncthreads();
+    const int own = a.lane_mass[base + t];
+    const int i = base + own;
+    double dot = 0.0;
+    if (i < a.n) {
+        const float4 xi = sx[own];
+        const double u0 = su[3 * own], u1 = su[3 * own + 1], u2 = su[3 * own + 2];
+        double k0 = 0.0, k1 = 0.0, k2 = 0.0;
+        const int s = (base + t) >> 6, lane = t & 63;
+        const int e0 = a.slice_ptr[s];
+        const int width = (a.slice_ptr[s + 1] - e0) >> 6;
+        for (int r = 0, e = e0 + lane; r < width; ++r, e += 64) {
+            const int slot = a.nbr[e];
+            if (slot == own) continue;  // padding
+            const float2 c = a.kl[e];
+            double l0 = (double)c.y;
+            if (a.grp) l0 *= (double)a.factor[a.grp[e]];
+            spring_hessian(xi, sx[slot], u0, u1, u2, su[3 * slot], su[3 * slot + 1], su[3 * slot + 2], (double)c.x,
+                           l0, k0, k1, k2);
+        }
+        if (a.ground && xi.z < a.ground_z) k2 += (double)a.ground_k * u2;
+        const double si = a.ism[i];
+        const double y0 = si * k0, y1 = si * k1, y2 = si * k2;
+        y[3 * i] = y0;
+        y[3 * i + 1] = y1;
+        y[3 * i + 2] = y2;
+        dot = q[3 * i] * y0 + q[3 * i + 1] * y1 + q[3 * i + 2] * y2;
+    }
+    const double sum = workgroup_sum(dot, red);
+    if (t == 0) part[b] = sum;
+}
+
+// y = A q for the masses of workgroup-block b, and the block's part of q . y; neighbours read
+// from global memory (used when the staged form's LDS would not fit).
 __global__ void __launch_bounds__(1024) modes_apply_kernel(ApplyArgs a, const double* __restrict__ q,
                                                            double* __restrict__ y, double* __restrict__ part) {
     __shared__ double red[kMaxWaves + 1];
@@ -115,19 +191,9 @@ __global__ void __launch_bounds__(1024) modes_apply_kernel(ApplyArgs a, const do
             const float2 c = a.kl[e];
             double l0 = (double)c.y;
             if (a.grp) l0 *= (double)a.factor[a.grp[e]];
-            const float4 xj = a.x[j];
-            const double dx = (double)xj.x - (double)xi.x, dy = (double)xj.y - (double)xi.y,
-                         dz = (double)xj.z - (double)xi.z;
-            const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-            const double nx = dx * il, ny = dy * il, nz = dz * il;
             const double sj = a.ism[j];
-            const double d0 = u0 - sj * q[3 * j], d1 = u1 - sj * q[3 * j + 1], d2 = u2 - sj * q[3 * j + 2];
-            const double nd = nx * d0 + ny * d1 + nz * d2;
-            const double g = 1.0 - l0 * il;
-            const double kk = (double)c.x;
-            k0 += kk * (nd * nx + g * (d0 - nd * nx));
-            k1 += kk * (nd * ny + g * (d1 - nd * ny));
-            k2 += kk * (nd * nz + g * (d2 - nd * nz));
+            spring_hessian(xi, a.x[j], u0, u1, u2, sj * q[3 * j], sj * q[3 * j + 1], sj * q[3 * j + 2], (double)c.x,
+                           l0, k0, k1, k2);
         }
         if (a.ground && xi.z < a.ground_z) k2 += (double)a.ground_k * u2;
         const double y0 = si * k0, y1 = si * k1, y2 = si * k2;
@@ -195,8 +261,12 @@ hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepPara
     double* q = m.q[(k + 1) & 1];   // q_k (the start vector q_0 sits in q[1])
     double* qw = m.q[k & 1];        // q_{k-1} in, q_{k+1} out
     ApplyArgs a{d.x[cur], m.ism, d.slice_ptr, d.nbr, d.kl, d.grp, d.factor, d.halo_ptr, d.halo_idx, d.lane_mass,
-                n, d.block, p.ground, p.ground_z, p.ground_k};
-    hipLaunchKernelGGL(modes_apply_kernel, dim3((unsigned)d.nblk), dim3(d.block), 0, st, a, q, m.y, m.part_a);
+                n, d.block, d.lds_slots, p.ground, p.ground_z, p.ground_k};
+    const size_t lds = (size_t)d.lds_slots * (sizeof(float4) + 3 * sizeof(double));
+    if (lds <= kModesMaxLds)
+        hipLaunchKernelGGL(modes_apply_lds_kernel, dim3((unsigned)d.nblk), dim3(d.block), lds, st, a, q, m.y, m.part_a);
+    else
+        hipLaunchKernelGGL(modes_apply_kernel, dim3((unsigned)d.nblk), dim3(d.block), 0, st, a, q, m.y, m.part_a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(modes_update_kernel, dim3(g), dim3(256), 0, st, m.part_a, (int)d.nblk, m.y, q, qw, m.alpha,
