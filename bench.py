@@ -370,6 +370,7 @@ def main(argv=None):
     ap.add_argument("--fast-diff", action="store_true", help="skip the exact coordinate difference")
     ap.add_argument("--no-table", action="store_true", help="explicit per-entry (k, L0) instead of the table")
     ap.add_argument("--split", action="store_true", help="split step form (spring pass + gather pass)")
+    ap.add_argument("--wide-entries", action="store_true", help="32-bit compact entries even where 16-bit ones fit")
     ap.add_argument("--integrator", choices=("euler", "verlet"), default="euler",
                     help="symplectic Euler (default) or Verlet, eqs. (5)-(6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -427,6 +428,7 @@ def main(argv=None):
     stream = torch.cuda.Stream()
     flags = ((CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0) |
              (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0) |
+             (CR.WIDE_ENTRIES if args.wide_entries else 0) |
              (CR.VERLET if args.integrator == "verlet" else 0) | (CR.RESIDENT if args.resident else 0))
     if args.workload == "candidate":
         w = W.candidate_bar(args.points)

@@ -64,6 +64,9 @@ typedef enum {
                                         keeps it in LDS and takes up to 4096 steps per launch
                                         (compact table form needed; ignored otherwise, see
                                         cronos_launch_config)                                 */
+#define CRONOS_WIDE_ENTRIES   0x200u /* keep 32-bit compact entries where 16-bit ones would fit
+                                        (passive systems whose workgroup LDS slots and (k, L0)
+                                        pairs fit in 16 bits; see CRONOS_FORM_NARROW)        */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -302,6 +305,8 @@ cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs,
 #define CRONOS_FORM_TABLE    1  /* 32-bit entries indexing the table of distinct (k, L0) pairs    */
 #define CRONOS_FORM_SPLIT    2  /* spring pass (each spring once per workgroup) + gather pass     */
 #define CRONOS_FORM_RESIDENT 3  /* table form, the whole system in one workgroup, many steps per launch */
+#define CRONOS_FORM_NARROW   4  /* table form with 16-bit entries (passive systems whose LDS slot and
+                                   pair index fit in 16 bits together): half the entry bytes        */
 cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
                                    int32_t* step_form);
 

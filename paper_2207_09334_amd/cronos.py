@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcronos.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT, VERLET, RESIDENT = (
-    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80, 0x100)
+ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT, VERLET, RESIDENT, WIDE_ENTRIES = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80, 0x100, 0x200)
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -284,7 +284,7 @@ def cronos_autotune(x0, mass, ends, k, rest, n_steps=20, **kw) -> dict:
     return cronos_create(x0, mass, ends, k, rest, _tune_steps=n_steps, **kw)
 
 
-FORMS = ("explicit", "table", "split", "resident")
+FORMS = ("explicit", "table", "split", "resident", "narrow")
 
 
 def cronos_candidate_points(size, n_points: int, n_candidates: int = 100, k_nn: int = 4, seed: int = 0) -> np.ndarray:

@@ -36,9 +36,11 @@ struct DeviceArrays {
     int32_t* slice_ptr = nullptr;
     uint16_t* nbr = nullptr;
     float2* kl = nullptr;                // (k, L0) per entry
-    uint32_t* packed = nullptr;          // compact entries: LDS slot | table index << 16 (or null)
+    uint32_t* packed = nullptr;          // compact 32-bit entries (or null)
+    uint16_t* narrow = nullptr;          // compact 16-bit entries: slot << narrow_tb | pair index (or null)
+    int32_t narrow_tb = 0;
     float4* table = nullptr;             // distinct (k, L0) pairs of the compact entries, as
-                                         // (k, L0, fl(L0^2), L0^2 - fl(L0^2))
+                                         // (k, L0, L0^2 as an FP64 value in the last two words)
     int32_t n_table = 0;
     int2* blk_groups = nullptr;          // per workgroup (first factor index, count) of its actuated springs
     int32_t max_local_groups = 0;

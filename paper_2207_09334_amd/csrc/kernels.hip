@@ -36,63 +36,38 @@ __device__ __forceinline__ int logical_block(int nblk) {
 // Coordinate-difference modes of the spring arithmetic (see hooke_fac).
 enum : int { kPlain = 0, kExactZ = 1, kExactAll = 2 };
 
-// Error-free sum of a and b when |a| >= |b| (Dekker's Fast2Sum): s + e == a + b exactly.
-__device__ __forceinline__ float fast_two_sum(float a, float b, float& e) {
-    const float s = a + b;
-    e = b - (s - a);
-    return s;
-}
-
-// Residual of a floating-point subtraction: returns e with (a - b) == s + e exactly, where
-// s = fl(a - b) (Knuth's TwoSum applied to a and -b).
-__device__ __forceinline__ float sub_residual(float a, float b, float s) {
-    const float bb = s - a;
-    return (a - (s - bb)) - (b + bb);
-}
-
 // Scalar factor of the Hooke force of eq. (2) for the spring from (xi, yi, zi) to (xj, yj, zj):
 // the force on the first end is fac * d with d = xj - xi; a zero-length spring gives 0 (its d
 // is 0 and fac stays finite).  Every step below is unchanged, bit for bit, when d changes sign,
 // so both ends of a spring see the same factor.
 //
-// Elongation: |d| - L0 = (|d|^2 - L0^2) / (|d| + L0), with |d|^2 - L0^2 formed from error-free
-// pieces: squares by FMA (dx^2 = px + ex exactly), their sum by Fast2Sum on the three squares
-// sorted by size (max3 / med3 / min3), and L0^2 = q + eq.  Near rest the leading difference
-// s2 - q is exact, so the error is a few ulps of the elongation itself, not of L0.
-// EX: d = xj - xi is exact whenever the two coordinates are within a factor of two of each
-// other (Sterbenz); near a coordinate plane it is not, and for a nearly relaxed spring that
-// one-ulp error in d would be a large fraction of the elongation.  kExactAll folds the
-// subtraction residuals r in (|d + r|^2 = |d|^2 + 2 d.r + O(r^2)), so the elongation is that
-// of the stored positions whatever their magnitude; kExactZ does so for z only, for
-// wavefronts near the z = 0 plane alone (the contact plane); kPlain skips them.
+// Elongation: |d| - L0 = (|d|^2 - L0^2) / (|d| + L0).  The numerator is formed in FP64 from the
+// FP32 differences: the square of a 24-bit value is exact in 53 bits, L0^2 (q) is held exactly,
+// so near rest the cancellation in |d|^2 - L0^2 loses nothing that matters (the error is
+// ~1e-16 of L0^2, against FP32's ~6e-8).  On this chip an FP64 FMA takes the issue slot of an
+// FP32 one, so five FP64 operations replace the twenty-odd FP32 ones of an error-free FP32
+// formulation.
+// EX: d = xj - xi is exact in FP32 whenever the two coordinates are within a factor of two of
+// each other (Sterbenz); near a coordinate plane it is not, and for a nearly relaxed spring
+// that one-ulp error in d would be a large fraction of the elongation.  kExactAll takes the
+// differences in FP64 (exact for any two FP32 values of similar scale), so the elongation is
+// that of the stored positions whatever their magnitude; kExactZ does so for z only, for
+// wavefronts near the z = 0 plane alone (the contact plane); kPlain widens the FP32 ones.
 template <int EX>
 __device__ __forceinline__ float hooke_fac(float xi, float yi, float zi, float xj, float yj, float zj, float k,
-                                           float l0, float q, float eq, float& dx, float& dy, float& dz) {
+                                           float l0, double q, float& dx, float& dy, float& dz) {
     dx = xj - xi;
     dy = yj - yi;
     dz = zj - zi;
-    const float px = dx * dx, py = dy * dy, pz = dz * dz;
-    const float ex = __builtin_fmaf(dx, dx, -px);
-    const float ey = __builtin_fmaf(dy, dy, -py);
-    const float ez = __builtin_fmaf(dz, dz, -pz);
-    const float big = __builtin_fmaxf(__builtin_fmaxf(px, py), pz);
-    const float mid = __builtin_amdgcn_fmed3f(px, py, pz);
-    const float small = __builtin_fminf(__builtin_fminf(px, py), pz);
-    float e1, e2;
-    const float s1 = fast_two_sum(big, mid, e1);
-    const float s2 = fast_two_sum(s1, small, e2);
-    // |d|^2 - L0^2 = (s2 - q) + (e1 + e2 + ex + ey + ez - eq)
-    float lo = ((e1 + e2) + (ex + ey)) + (ez - eq);
+    double ex = dx, ey = dy, ez = dz;
     if (EX == kExactAll) {
-        const float rx = sub_residual(xj, xi, dx);
-        const float ry = sub_residual(yj, yi, dy);
-        const float rz = sub_residual(zj, zi, dz);
-        const float dr = __builtin_fmaf(dz, rz, __builtin_fmaf(dy, ry, dx * rx));
-        lo = __builtin_fmaf(2.0f, dr, lo);
-    } else if (EX == kExactZ) {  // x and y differences are exact (their residuals are 0)
-        lo = __builtin_fmaf(2.0f, dz * sub_residual(zj, zi, dz), lo);
+        ex = (double)xj - (double)xi;
+        ey = (double)yj - (double)yi;
     }
-    const float diff = (s2 - q) + lo;
+    if (EX != kPlain) ez = (double)zj - (double)zi;
+    const double s = __builtin_fma(ex, ex, __builtin_fma(ey, ey, ez * ez));
+    const float diff = (float)(s - q);
+    const float s2 = (float)s;
     const float len = __builtin_amdgcn_sqrtf(s2);
     // |d| (|d| + L0) = s2 + L0 |d| to within an ulp; the floor keeps a zero-length spring's
     // factor finite (its force fac * d is then exactly 0) and is far below any real spring's
@@ -100,15 +75,15 @@ __device__ __forceinline__ float hooke_fac(float xi, float yi, float zi, float x
     return k * diff * __builtin_amdgcn_rcpf(den);
 }
 
-// Hooke force of eq. (2) on mass i from one spring to a neighbour at (xj, yj, zj),
-// accumulated into f.
+// The same with L0^2 formed here (exact in FP64).
 template <int EX>
 __device__ __forceinline__ float hooke_fac(float xi, float yi, float zi, float xj, float yj, float zj, float k,
                                            float l0, float& dx, float& dy, float& dz) {
-    const float q = l0 * l0;
-    return hooke_fac<EX>(xi, yi, zi, xj, yj, zj, k, l0, q, __builtin_fmaf(l0, l0, -q), dx, dy, dz);
+    return hooke_fac<EX>(xi, yi, zi, xj, yj, zj, k, l0, (double)l0 * (double)l0, dx, dy, dz);
 }
 
+// Hooke force of eq. (2) on mass i from one spring to a neighbour at (xj, yj, zj),
+// accumulated into f.
 template <int EX>
 __device__ __forceinline__ void hooke(float xi, float yi, float zi, float xj, float yj, float zj,
                                       float k, float l0, float& fx, float& fy, float& fz) {
@@ -119,13 +94,20 @@ __device__ __forceinline__ void hooke(float xi, float yi, float zi, float xj, fl
     fz = __builtin_fmaf(fac, dz, fz);
 }
 
-// The same with a parameter-table entry c = (k, L0, L0^2, its FMA residual); an actuated spring
-// scales L0 by its factor g and squares it here.
+// L0^2 of a parameter-table entry c = (k, L0, L0^2 as an FP64 value in its last two words).
+__device__ __forceinline__ double table_l0sq(float4 c) {
+    const unsigned long long bits =
+        ((unsigned long long)__float_as_uint(c.w) << 32) | (unsigned long long)__float_as_uint(c.z);
+    return __longlong_as_double((long long)bits);
+}
+
+// The same with a parameter-table entry c = (k, L0, L0^2 in FP64); an actuated spring scales L0
+// by its factor g and squares it here.
 template <bool ACT, int EX>
 __device__ __forceinline__ float hooke_fac_tab(float4 xi, float4 xj, float4 c, float g, float& dx, float& dy,
                                                float& dz) {
     if (ACT) return hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, c.y * g, dx, dy, dz);
-    return hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, c.y, c.z, c.w, dx, dy, dz);
+    return hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, c.x, c.y, table_l0sq(c), dx, dy, dz);
 }
 
 // Stage the workgroup's masses (in mass order) and its halo in LDS; returns the block-relative
@@ -260,6 +242,42 @@ __device__ __forceinline__ void gather_table(uint32_t tbase, const float* __rest
     for (; r < w; ++r) one(pp[r * 64]);
 }
 
+// The same sum over 16-bit entries (passive simulations whose LDS slots and (k, L0) pairs fit
+// together in 16 bits): neighbour slot << tb | pair index.  Half the entry stream of the
+// 32-bit form, which is most of what a step reads from HBM.
+template <int EX, int BATCH>
+__device__ __forceinline__ void gather_narrow(uint32_t tbase, float4 xi, int s, int nslice,
+                                              const int32_t* __restrict__ slice_ptr,
+                                              const uint16_t* __restrict__ narrow, int tb, float& fx, float& fy,
+                                              float& fz) {
+    fx = fy = fz = 0.0f;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s >= nslice) return;
+    const int lane = threadIdx.x & 63;
+    const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
+    const int w = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
+    const uint16_t* pp = narrow + e0 + lane;
+    const uint32_t tmask = (1u << tb) - 1u;
+    auto one = [&](uint32_t q) {
+        const float4 xj = lds_f4((q >> tb) << 4);
+        const float4 c = lds_f4(((q & tmask) << 4) | tbase);
+        float dx, dy, dz;
+        const float fac = hooke_fac_tab<false, EX>(xi, xj, c, 1.0f, dx, dy, dz);
+        fx = __builtin_fmaf(fac, dx, fx);
+        fy = __builtin_fmaf(fac, dy, fy);
+        fz = __builtin_fmaf(fac, dz, fz);
+    };
+    int r = 0;
+    for (; r + BATCH <= w; r += BATCH) {
+        uint32_t q[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) q[u] = pp[(r + u) * 64];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) one(q[u]);
+    }
+    for (; r < w; ++r) one(pp[r * 64]);
+}
+
 // Split form of the same sum, in two passes over the workgroup's LDS.
 // Spring pass: every spring with an end among the workgroup's masses is evaluated once (a
 // spring between two of them is shared; one to a halo mass is evaluated here and again by
@@ -373,12 +391,14 @@ struct StepArgs {
     const float* __restrict__ fext;
     float* __restrict__ vstar_out;   // optional: velocity before friction and damping (adjoint recompute)
     const uint32_t* __restrict__ packed;   // compact entries (see gather_table), or null
-    const float4* __restrict__ table;      // (k, L0, L0^2, residual) of the compact entries
+    const uint16_t* __restrict__ narrow;   // 16-bit compact entries (see gather_narrow), or null
+    const float4* __restrict__ table;      // (k, L0, L0^2 in FP64) of the compact entries
     const int2* __restrict__ blk_groups;   // per workgroup: first factor index and count
     const uint32_t* __restrict__ sp_rec;   // split form: spring records, workgroup after workgroup
     const uint16_t* __restrict__ sp_grp;   // split form: local actuation factor index per record
     const int32_t* __restrict__ sp_ptr;    // split form: first record of each workgroup
     int n, nblk, nslice, block, n_table, lds_slots, max_local_groups;
+    int narrow_tb;                         // pair-index bits of the 16-bit entries
 };
 
 // Difference mode of a wavefront (uniform across it).  A coordinate at least `safe` away from
@@ -408,7 +428,7 @@ struct ResidentArgs {
 };
 
 // Step modes: explicit (k, L0) per entry, compact entries with the parameter table, split.
-enum : int { kExplicit = 0, kTable = 1, kSplit = 2 };
+enum : int { kExplicit = 0, kTable = 1, kSplit = 2, kNarrow = 3 };
 
 // Elapsed fraction of an actuation period at step n, frac(n f dt), formed exactly in 64-bit
 // fixed point (n * cycles wraps modulo 2^64), and the factor 1 + A sin(2 pi u + phi).
@@ -501,7 +521,15 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
                             fx, fy, fz);
     } else {
         const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
-        if (TABLE) {
+        if (MODE == kNarrow) {   // passive only (the host never picks it for actuation)
+            if (mode == kPlain)
+                gather_narrow<kPlain, BATCH>(tbase, xi, s, a.nslice, a.slice_ptr, a.narrow, a.narrow_tb, fx, fy, fz);
+            else if (mode == kExactZ)
+                gather_narrow<kExactZ, BATCH>(tbase, xi, s, a.nslice, a.slice_ptr, a.narrow, a.narrow_tb, fx, fy, fz);
+            else
+                gather_narrow<kExactAll, kExactBatch<BATCH>>(tbase, xi, s, a.nslice, a.slice_ptr, a.narrow, a.narrow_tb,
+                                                             fx, fy, fz);
+        } else if (TABLE) {
             if (mode == kPlain) gather_table<ACT, kPlain, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
             else if (mode == kExactZ)
                 gather_table<ACT, kExactZ, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
@@ -947,7 +975,8 @@ hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipS
 hipError_t step_static_lds(size_t* bytes) {
     const void* ks[] = {(const void*)step_kernel<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kTable>,
                         (const void*)step_persistent<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kSplit>,
-                        (const void*)step_persistent<true, false, 8, kSplit>};
+                        (const void*)step_persistent<true, false, 8, kSplit>,
+                        (const void*)step_kernel<false, true, 4, kNarrow>};
     *bytes = 0;
     for (const void* k : ks) {
         hipFuncAttributes at{};
@@ -960,7 +989,7 @@ hipError_t step_static_lds(size_t* bytes) {
 
 size_t step_lds_bytes(const DeviceArrays& d) {
     size_t b = (size_t)d.lds_slots * sizeof(float4);
-    if (d.packed)
+    if (d.packed || d.narrow)
         b = table_base(d.lds_slots) + (size_t)d.n_table * sizeof(float4) + (size_t)(d.max_local_groups + 1) * sizeof(float);
     if (d.sp_rec) b += (size_t)(d.max_sp + 1) * sizeof(float);
     return b;
@@ -968,10 +997,11 @@ size_t step_lds_bytes(const DeviceArrays& d) {
 
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
                           float* vstar, const StepParams& p, hipStream_t st) {
-    const int mode = d.sp_rec ? kSplit : d.packed ? kTable : kExplicit;
+    const int mode = d.sp_rec ? kSplit : d.narrow ? kNarrow : d.packed ? kTable : kExplicit;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
-               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr,
-               (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups};
+               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
+               d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
+               d.narrow_tb};
     const size_t lds = step_lds_bytes(d);
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
@@ -980,8 +1010,13 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
         else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds, st, a, p);
     };
 #define CRONOS_GO(A, E, B, M) go(step_kernel<A, E, B, M>, step_persistent<A, E, B, M>)
-#define CRONOS_GO_M(A, E, B) \
-    (mode == kSplit ? CRONOS_GO(A, E, B, kSplit) : mode == kTable ? CRONOS_GO(A, E, B, kTable) : CRONOS_GO(A, E, B, kExplicit))
+// (16-bit entries exist for passive simulations only: the actuated expansion maps them to kTable,
+// which it never meets there)
+#define CRONOS_GO_M(A, E, B)                                                                         \
+    (mode == kSplit    ? CRONOS_GO(A, E, B, kSplit)                                                  \
+     : mode == kNarrow ? CRONOS_GO(A, E, B, (A ? kTable : kNarrow))                                  \
+     : mode == kTable  ? CRONOS_GO(A, E, B, kTable)                                                  \
+                       : CRONOS_GO(A, E, B, kExplicit))
     const bool act = d.grp != nullptr, ex = p.exact != 0;
     if (d.batch == 8) {
         if (act) ex ? CRONOS_GO_M(true, true, 8) : CRONOS_GO_M(true, false, 8);
@@ -1001,8 +1036,9 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
 hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, float dtv0, unsigned long long cycles,
                            int steps, hipStream_t st) {
     StepArgs a{d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
-               d.lane_mass, d.factor, d.fext, nullptr, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr,
-               (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups};
+               d.lane_mass, d.factor, d.fext, nullptr, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
+               d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
+               d.narrow_tb};
     ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr, steps, dtv0};
     const size_t lds = step_lds_bytes(d);
     const bool act = d.grp != nullptr, ex = p.exact != 0;

@@ -107,7 +107,7 @@ namespace {
 
 void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
-    void* ptrs[] = {d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
+    void* ptrs[] = {d.narrow, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
                     d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.act_done, d.chunks, d.body_chunk, d.chunk_part,
                     d.body_out, d.fout};
     for (void* p : ptrs)
@@ -734,11 +734,35 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             D.max_sp = max_sp;
         }
         if (!htable.empty()) {
-            if (hsp_rec.empty()) TRY(upload(&D.packed, hpacked.data(), entries));
+            // passive simulations whose LDS slots and pair indices fit in 16 bits together take
+            // 16-bit entries (slot << tb | pair index): half the bytes of the entry stream
+            const bool resident = (d->flags & CRONOS_RESIDENT) && L.nblk == 1 && hsp_rec.empty();
+            std::vector<uint16_t> hnarrow;
+            if (!sim->actuated && hsp_rec.empty() && !resident && !(d->flags & CRONOS_WIDE_ENTRIES)) {
+                int sb = 1;
+                while ((1 << sb) < L.block + L.max_halo) ++sb;
+                const int tb = std::min(16 - sb, (int)kTypeBits);
+                if (tb >= 1 && (int64_t)htable.size() <= (int64_t)1 << tb) {
+                    hnarrow.resize(entries);
+                    cronos::parallel_for(entries, [&](int64_t e0, int64_t e1) {
+                        for (int64_t e = e0; e < e1; ++e) {
+                            const uint32_t q = hpacked[e];
+                            hnarrow[e] = (uint16_t)(((q >> 19) << tb) | ((q >> 4) & ((1u << kTypeBits) - 1u)));
+                        }
+                    });
+                    D.narrow_tb = tb;
+                }
+            }
+            if (!hnarrow.empty()) TRY(upload(&D.narrow, hnarrow.data(), entries));
+            else if (hsp_rec.empty()) TRY(upload(&D.packed, hpacked.data(), entries));
             std::vector<float4> tab(htable.size());
             for (size_t q = 0; q < htable.size(); ++q) {
-                const float l0 = htable[q].y, sq = l0 * l0;
-                tab[q] = make_float4(htable[q].x, l0, sq, std::fmaf(l0, l0, -sq));
+                // (k, L0, L0^2 exactly, as an FP64 value in the last two words)
+                const float l0 = htable[q].y;
+                const double sq = (double)l0 * (double)l0;
+                float w[2];
+                std::memcpy(w, &sq, sizeof sq);
+                tab[q] = make_float4(htable[q].x, l0, w[0], w[1]);
             }
             TRY(upload(&D.table, tab.data(), tab.size()));
             D.n_table = (int32_t)htable.size();
@@ -1301,6 +1325,7 @@ extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_mas
     if (step_form)
         *step_form = sim->d.resident ? CRONOS_FORM_RESIDENT
                      : sim->d.sp_rec ? CRONOS_FORM_SPLIT
+                     : sim->d.narrow ? CRONOS_FORM_NARROW
                      : sim->d.packed ? CRONOS_FORM_TABLE
                                      : CRONOS_FORM_EXPLICIT;
     return CRONOS_OK;
