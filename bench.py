@@ -128,7 +128,7 @@ def adjoint_bench(args) -> dict:
 
     CR.cronos_set_actuation(sim, ph, am, w.freq_hz)
     plain()
-    grad()                                        # warm-up (allocations, graphs)
+    first = grad()                                # warm-up: allocations, the sweep's graph capture
     t_plain = min(plain() for _ in range(3))
     runs = [grad() for _ in range(3)]
     t_fwd = min(r[0] for r in runs)
@@ -143,6 +143,7 @@ def adjoint_bench(args) -> dict:
                    "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph)),
                    "block_masses": CR.cronos_launch_config(sim)["block_masses"]},
         "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
+        "first_backward_s": first[1],
         "gradient_over_plain_forward": (t_fwd + t_bwd) / t_plain, "loss": loss,
         "bitwise_repeatable": bool(repeat),
     }

@@ -79,8 +79,9 @@ hipError_t step_static_lds(size_t* bytes);
 
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 // The step with explicit buffers; vstar (optional) receives the velocity before friction/damping.
+// factor (optional) replaces the simulation's actuation factor table.
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
-                          float* vstar, const StepParams& p, hipStream_t st);
+                          float* vstar, const StepParams& p, hipStream_t st, const float* factor = nullptr);
 // `steps` steps of a system held by one workgroup (resident form; table form, block >= n):
 // positions stay in LDS between steps; the first step kicks for dtv0.  Reads x[cur], v[cur],
 // writes x[cur ^ 1], v[cur ^ 1]; advances the device step counter by `steps`.
@@ -91,13 +92,14 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid);
 // Actuation table for the device step counter (advancing it when advance != 0), or for the
 // explicit step n_explicit >= 0 (counter untouched).  cycles = frac(f dt) * 2^64, the part of
 // an actuation period that one step advances, in 64-bit fixed point.
+// out (optional) receives the factors instead of the simulation's table.
 hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
-                            long long n_explicit = -1);
+                            long long n_explicit = -1, float* out = nullptr);
 // Adjoint of one step (see kernels.hip).
 hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,
                             const float* vb1, float4* w, float* vb0, float* xbl, const StepParams& p, hipStream_t st);
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st);
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor = nullptr);
 hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 
 // Lanczos iterations for the natural frequencies (modes.hip), FP64.

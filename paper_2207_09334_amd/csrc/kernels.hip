@@ -919,40 +919,62 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     const float4 xi = sx[own];
     const float4 wi = sw[own];
     float ax = 0.f, ay = 0.f, az = 0.f;
+    // one incidence: the spring's tangent stiffness applied to w_j - w_i, and (actuated) the
+    // sensitivity of the loss to its rest length, accumulated in FP64
+    auto one = [&](int e, int slot, float2 c, int g, float f, double2 acc) {
+        const float l0 = ACT ? c.y * f : c.y;
+        const float4 xj = sx[slot];
+        const float4 wj = sw[slot];
+        const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+        const float len2 = dx * dx + dy * dy + dz * dz;
+        if (len2 > 0.0f) {
+            const float len = __builtin_sqrtf(len2);
+            const float il = 1.0f / len;
+            const float nx = dx * il, ny = dy * il, nz = dz * il;
+            const float dwx = wj.x - wi.x, dwy = wj.y - wi.y, dwz = wj.z - wi.z;
+            const float ndw = nx * dwx + ny * dwy + nz * dwz;
+            const float tr = 1.0f - l0 * il;        // delta / l
+            const float k = c.x;
+            ax += k * (nx * ndw + tr * (dwx - nx * ndw));
+            ay += k * (ny * ndw + tr * (dwy - ny * ndw));
+            az += k * (nz * ndw + tr * (dwz - nz * ndw));
+            if (ACT && g < n_factor) {
+                const double q = 0.5 * (double)c.y * (double)k * (double)ndw;
+                acc.x += cos_t * q;
+                acc.y += sin_t * q;
+                sens[e] = acc;
+            }
+        }
+    };
     const int s = __builtin_amdgcn_readfirstlane((base + t) >> 6);
     if (s < nslice) {
         const int lane = t & 63;
         const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
         const int wdt = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
-        for (int r = 0; r < wdt; ++r) {
-            const int e = e0 + r * 64 + lane;
-            const int slot = nbr[e];
-            const float2 c = kl[e];
-            const int g = ACT ? (int)grp[e] : n_factor;
-            const float l0 = ACT ? c.y * factor[g] : c.y;
-            const float4 xj = sx[slot];
-            const float4 wj = sw[slot];
-            const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-            const float len2 = dx * dx + dy * dy + dz * dz;
-            if (len2 > 0.0f) {
-                const float len = __builtin_sqrtf(len2);
-                const float il = 1.0f / len;
-                const float nx = dx * il, ny = dy * il, nz = dz * il;
-                const float dwx = wj.x - wi.x, dwy = wj.y - wi.y, dwz = wj.z - wi.z;
-                const float ndw = nx * dwx + ny * dwy + nz * dwz;
-                const float tr = 1.0f - l0 * il;        // delta / l
-                const float k = c.x;
-                ax += k * (nx * ndw + tr * (dwx - nx * ndw));
-                ay += k * (ny * ndw + tr * (dwy - ny * ndw));
-                az += k * (nz * ndw + tr * (dwz - nz * ndw));
-                if (ACT && g < n_factor) {
-                    const double q = 0.5 * (double)c.y * (double)k * (double)ndw;
-                    double2 acc = sens[e];
-                    acc.x += cos_t * q;
-                    acc.y += sin_t * q;
-                    sens[e] = acc;
-                }
+        constexpr int B = 4;   // entries whose loads are in flight together
+        int r = 0;
+        for (; r + B <= wdt; r += B) {
+            int slot[B], g[B];
+            float2 c[B];
+            float f[B];
+            double2 acc[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + (r + u) * 64 + lane;
+                slot[u] = nbr[e];
+                c[u] = kl[e];
+                g[u] = ACT ? (int)grp[e] : n_factor;
+                if (ACT) acc[u] = sens[e];
             }
+#pragma unroll
+            for (int u = 0; u < B; ++u) f[u] = ACT ? factor[g[u]] : 1.0f;
+#pragma unroll
+            for (int u = 0; u < B; ++u) one(e0 + (r + u) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
+        }
+        for (; r < wdt; ++r) {
+            const int e = e0 + r * 64 + lane;
+            const int g = ACT ? (int)grp[e] : n_factor;
+            one(e, nbr[e], kl[e], g, ACT ? factor[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
         }
     }
     const int i = base + own;
@@ -996,10 +1018,10 @@ size_t step_lds_bytes(const DeviceArrays& d) {
 }
 
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
-                          float* vstar, const StepParams& p, hipStream_t st) {
+                          float* vstar, const StepParams& p, hipStream_t st, const float* factor) {
     const int mode = d.sp_rec ? kSplit : d.narrow ? kNarrow : d.packed ? kTable : kExplicit;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
-               d.lane_mass, d.factor, d.fext, vstar, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
+               d.lane_mass, factor ? factor : d.factor, d.fext, vstar, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
                d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
                d.narrow_tb};
     const size_t lds = step_lds_bytes(d);
@@ -1069,10 +1091,10 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
 }
 
 hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
-                            long long n_explicit) {
+                            long long n_explicit, float* out) {
     const unsigned grid = (unsigned)((d.n_factor + 1 + 255) / 256);
     hipLaunchKernelGGL(actuation_kernel, dim3(grid), dim3(256), 0, st, d.phase, d.amp, cycles, d.step_ctr, d.act_done,
-                       d.factor, d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
+                       out ? out : d.factor, d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
     return hipGetLastError();
 }
 
@@ -1116,15 +1138,16 @@ hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float*
 }
 
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st) {
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor) {
     const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4);
+    if (!factor) factor = d.factor;
     if (d.grp)
         hipLaunchKernelGGL(adj_gather_kernel<true>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, sens,
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
                            d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
     else
         hipLaunchKernelGGL(adj_gather_kernel<false>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, d.factor, sens,
+                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
                            d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
     return hipGetLastError();
 }

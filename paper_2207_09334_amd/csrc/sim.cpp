@@ -66,6 +66,7 @@ struct RolloutBuffers {
     float4* seg_x = nullptr;  // [K+1][N]
     float* seg_v = nullptr;   // [K+1][3N]
     float* seg_vs = nullptr;  // [K][3N]
+    float* seg_f = nullptr;   // [K][n_factor + 1] actuation factors of the segment's steps
     float* lossw = nullptr;   // [3N]
     float4* w = nullptr;      // [N]
     float* xb[2] = {nullptr, nullptr};
@@ -73,6 +74,10 @@ struct RolloutBuffers {
     float* xbl = nullptr;
     double2* sens = nullptr;  // [entries]
     size_t cap_seg = 0, cap_ck = 0;
+    // the reverse sweep captured as one HIP graph, reused while everything it bakes in (the
+    // rollout's extent, the buffers, the actuation frequency) is unchanged
+    hipGraphExec_t bwd_graph = nullptr;
+    std::vector<double> bwd_key;
 };
 
 struct cronos_sim_t {
@@ -115,7 +120,8 @@ void free_device(cronos_sim_t* s) {
     for (auto& g : s->graph)
         if (g) (void)hipGraphExecDestroy(g);
     RolloutBuffers& r = s->ro;
-    void* rp[] = {r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w, r.xb[0], r.xb[1], r.vb[0], r.vb[1], r.xbl,
+    if (r.bwd_graph) (void)hipGraphExecDestroy(r.bwd_graph);
+    void* rp[] = {r.seg_f, r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w, r.xb[0], r.xb[1], r.vb[0], r.vb[1], r.xbl,
                   r.sens};
     for (void* p : rp)
         if (p) (void)hipFree(p);
@@ -1196,7 +1202,7 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     const int32_t nseg = (int32_t)((n_steps + K - 1) / K);
     if (R.cap_seg < (size_t)K || R.cap_ck < (size_t)nseg) {
         HIP_TRY(hipStreamSynchronize(sim->stream));
-        release(R.ck_x); release(R.ck_v); release(R.seg_x); release(R.seg_v); release(R.seg_vs);
+        release(R.ck_x); release(R.ck_v); release(R.seg_x); release(R.seg_v); release(R.seg_vs); release(R.seg_f);
         R.cap_seg = std::max<size_t>(R.cap_seg, (size_t)K);
         R.cap_ck = std::max<size_t>(R.cap_ck, (size_t)std::max(nseg, 1));
     }
@@ -1205,6 +1211,7 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     TRY(ensure(&R.seg_x, (R.cap_seg + 1) * n));
     TRY(ensure(&R.seg_v, (R.cap_seg + 1) * 3 * n));
     TRY(ensure(&R.seg_vs, R.cap_seg * 3 * n));
+    TRY(ensure(&R.seg_f, R.cap_seg * (size_t)(sim->d.n_factor + 1)));
     TRY(ensure(&R.lossw, 3 * n));
     TRY(ensure(&R.w, n));
     for (int q = 0; q < 2; ++q) {
@@ -1239,6 +1246,46 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     return CRONOS_OK;
 }
 
+namespace {
+
+// Enqueues the reverse sweep of the recorded rollout on the simulation's stream: for each
+// segment from the last, restore its checkpoint, recompute its states forward (keeping v* and
+// each step's actuation factors), then run the adjoint of each of its steps backwards.  No
+// host synchronisation and no memsets, so it can be captured in a HIP graph.
+cronos_status enqueue_reverse_sweep(cronos_sim_t* sim) {
+    RolloutBuffers& R = sim->ro;
+    const int64_t n = sim->d.n;
+    const cronos::DeviceArrays& D = sim->d;
+    hipStream_t st = sim->stream;
+    int cur = 0;
+    for (int32_t c = R.nseg - 1; c >= 0; --c) {
+        const int64_t nc = R.n0 + (int64_t)c * R.K;
+        const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
+        HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+        const size_t fs = (size_t)D.n_factor + 1;
+        for (int32_t k = 0; k < steps; ++k) {
+            float* fk = sim->actuated ? R.seg_f + (size_t)k * fs : nullptr;
+            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k, fk));
+            HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
+                                           R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
+                                           R.seg_vs + (size_t)k * 3 * n, sim->p, st, fk));
+        }
+        for (int32_t k = steps - 1; k >= 0; --k) {
+            const double t = (double)(nc + k) * sim->dt;
+            HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)k * n, R.seg_vs + (size_t)k * 3 * n, R.xb[cur],
+                                             R.vb[cur], R.w, R.vb[cur ^ 1], R.xbl, sim->p, st));
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w, R.xbl, R.xb[cur ^ 1], R.sens,
+                                              std::cos(sim->omega * t), std::sin(sim->omega * t), st,
+                                              sim->actuated ? R.seg_f + (size_t)k * fs : nullptr));
+            cur ^= 1;
+        }
+    }
+    return CRONOS_OK;
+}
+
+}  // namespace
+
 extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase, double* damp, double* dx0,
                                                  double* dv0) {
     cronos::clear_error();
@@ -1247,33 +1294,44 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     if (!R.valid) return fail(CRONOS_EINVAL, "rollout_backward: no rollout recorded");
     const int64_t n = sim->d.n;
     const int64_t entries = sim->lay.slice_ptr.back();
-    const cronos::DeviceArrays& D = sim->d;
     hipStream_t st = sim->stream;
     HIP_TRY(hipSetDevice(sim->device));
     HIP_TRY(hipMemcpyAsync(R.xb[0], R.lossw, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(R.vb[0], 0, 3 * n * sizeof(float), st));
     HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
-    int cur = 0;
-    for (int32_t c = R.nseg - 1; c >= 0; --c) {
-        const int64_t nc = R.n0 + (int64_t)c * R.K;
-        const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
-        HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
-        for (int32_t k = 0; k < steps; ++k) {
-            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k));
-            HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
-                                           R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
-                                           R.seg_vs + (size_t)k * 3 * n, sim->p, st));
+    // the reverse sweep flips the adjoint buffers once per step
+    const int cur = (int)(R.T & 1);
+    if (sim->use_graph) {
+        const std::vector<double> key = {(double)R.n0, (double)R.T, (double)R.K, (double)R.nseg,
+                                         (double)(sim->cycles >> 32), (double)(sim->cycles & 0xFFFFFFFFull), sim->omega,
+                                         (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x, (double)(uintptr_t)R.seg_f,
+                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens};
+        if (!R.bwd_graph || R.bwd_key != key) {
+            if (R.bwd_graph) {
+                HIP_TRY(hipStreamSynchronize(st));
+                (void)hipGraphExecDestroy(R.bwd_graph);
+                R.bwd_graph = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const cronos_status cs = enqueue_reverse_sweep(sim);
+            const hipError_t e = hipStreamEndCapture(st, &g);
+            if (cs != CRONOS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return cs;
+            }
+            if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            const hipError_t ei = hipGraphInstantiate(&R.bwd_graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                R.bwd_graph = nullptr;
+                return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+            }
+            R.bwd_key = key;
         }
-        for (int32_t k = steps - 1; k >= 0; --k) {
-            const double t = (double)(nc + k) * sim->dt;
-            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k));
-            HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)k * n, R.seg_vs + (size_t)k * 3 * n, R.xb[cur],
-                                             R.vb[cur], R.w, R.vb[cur ^ 1], R.xbl, sim->p, st));
-            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w, R.xbl, R.xb[cur ^ 1], R.sens,
-                                              std::cos(sim->omega * t), std::sin(sim->omega * t), st));
-            cur ^= 1;
-        }
+        HIP_TRY(hipGraphLaunch(R.bwd_graph, st));
+    } else {
+        TRY(enqueue_reverse_sweep(sim));
     }
     // per-group reduction of the actuation sensitivities, FP64, in entry order
     const int32_t G = sim->d.n_factor;
