@@ -17,6 +17,7 @@ struct StepParams {
     float safe;          // a wavefront whose masses all have |x_c| >= safe on every axis takes
                          // the plain difference (Sterbenz-exact for springs shorter than safe/2)
     double ox, oy, oz;   // origin of the device coordinates: absolute x = device x + o
+    unsigned long long cycles = 0;   // actuation: frac(f dt) * 2^64, the period fraction per step
 };
 
 // Device-resident layout and state of one simulation (all arrays in Morton order).
@@ -57,8 +58,8 @@ struct DeviceArrays {
     float* phase = nullptr;
     float* amp = nullptr;
     float* factor = nullptr;             // 1 + A sin(...) per (body, group), FP32
-    long long* step_ctr = nullptr;       // device step counter n
-    unsigned* act_done = nullptr;        // workgroups of the actuation launch that have finished
+    long long* step_ctr = nullptr;       // [2] device step counter pair: slot cur holds the step
+                                         // index of x[cur]; a launch reads slot cur, writes cur ^ 1
     // diagnostics
     int32_t n_chunks = 0;
     int32_t nb = 1;
@@ -79,9 +80,16 @@ hipError_t step_static_lds(size_t* bytes);
 
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 // The step with explicit buffers; vstar (optional) receives the velocity before friction/damping.
-// factor (optional) replaces the simulation's actuation factor table.
+// factor (optional) replaces the simulation's actuation factor table.  fuse != 0 (actuated
+// table forms only, see fused_actuation): the step computes its factors for the step index in
+// counter slot cur itself and stores the next index in slot cur ^ 1, as launch_actuation with
+// advance would.
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
-                          float* vstar, const StepParams& p, hipStream_t st, const float* factor = nullptr);
+                          float* vstar, const StepParams& p, hipStream_t st, const float* factor = nullptr,
+                          int fuse = 0, int cur = 0);
+// Whether launch_step computes the actuation factors inside the step (actuated systems in a
+// compact table form); otherwise an actuation launch must precede each step.
+bool fused_actuation(const DeviceArrays& d);
 // `steps` steps of a system held by one workgroup (resident form; table form, block >= n):
 // positions stay in LDS between steps; the first step kicks for dtv0.  Reads x[cur], v[cur],
 // writes x[cur ^ 1], v[cur ^ 1]; advances the device step counter by `steps`.
@@ -89,12 +97,12 @@ hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, 
                            int steps, hipStream_t st);
 // Workgroups of a persistent launch that are resident at once on the device (multiple of 8).
 hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid);
-// Actuation table for the device step counter (advancing it when advance != 0), or for the
-// explicit step n_explicit >= 0 (counter untouched).  cycles = frac(f dt) * 2^64, the part of
-// an actuation period that one step advances, in 64-bit fixed point.
-// out (optional) receives the factors instead of the simulation's table.
+// Actuation table for the step index in counter slot cur (storing the next index in slot
+// cur ^ 1 when advance != 0), or for the explicit step n_explicit >= 0 (counters untouched).
+// cycles = frac(f dt) * 2^64, the part of an actuation period that one step advances, in
+// 64-bit fixed point.  out (optional) receives the factors instead of the simulation's table.
 hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
-                            long long n_explicit = -1, float* out = nullptr);
+                            long long n_explicit = -1, float* out = nullptr, int cur = 0);
 // Adjoint of one step (see kernels.hip).
 hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,
                             const float* vb1, float4* w, float* vb0, float* xbl, const StepParams& p, hipStream_t st);

@@ -399,6 +399,15 @@ struct StepArgs {
     const int32_t* __restrict__ sp_ptr;    // split form: first record of each workgroup
     int n, nblk, nslice, block, n_table, lds_slots, max_local_groups;
     int narrow_tb;                         // pair-index bits of the 16-bit entries
+    // fused actuation (actuated table forms): each workgroup computes its factors for step
+    // n = *step_in from phase and amp; one thread stores n + 1 to *step_out (the other slot of
+    // the counter pair, so no workgroup of this launch reads it)
+    int fuse;
+    const float* __restrict__ phase;
+    const float* __restrict__ amp;
+    const long long* step_in;
+    long long* step_out;
+    unsigned long long cycles;
 };
 
 // Difference mode of a wavefront (uniform across it).  A coordinate at least `safe` away from
@@ -422,7 +431,8 @@ struct ResidentArgs {
     const float* __restrict__ phase;
     const float* __restrict__ amp;
     unsigned long long cycles;
-    long long* __restrict__ step_ctr;
+    const long long* step_in;   // step index of the input state (one slot of the counter pair)
+    long long* step_out;        // receives the index after the launch (the other slot)
     int steps;
     float dtv0;
 };
@@ -492,7 +502,8 @@ __device__ __forceinline__ void integrate(const StepParams& p, float dtv, float4
 // One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
 // damping, symplectic Euler, fixed masses.
 template <bool ACT, bool EXACT, int BATCH, int MODE>
-__device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b) {
+__device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b,
+                                           long long n_step) {
     constexpr bool TABLE = MODE != kExplicit;
     const int base = b * a.block;
     const uint32_t tbase = table_base(a.lds_slots);
@@ -503,7 +514,13 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
         for (int q = threadIdx.x; q < a.n_table; q += a.block) st[q] = a.table[q];
         if (ACT) {
             const int2 bg = a.blk_groups[b];
-            for (int q = threadIdx.x; q <= bg.y; q += a.block) sf[q] = q ? a.factor[bg.x + q - 1] : 1.0f;
+            if (a.fuse) {   // the same formula as actuation_kernel, for this workgroup's factors only
+                const float u = period_fraction(n_step, a.cycles);
+                for (int q = threadIdx.x; q <= bg.y; q += a.block)
+                    sf[q] = q ? actuation_factor(a.amp[bg.x + q - 1], a.phase[bg.x + q - 1], u) : 1.0f;
+            } else {
+                for (int q = threadIdx.x; q <= bg.y; q += a.block) sf[q] = q ? a.factor[bg.x + q - 1] : 1.0f;
+            }
         }
     }
     const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
@@ -553,12 +570,20 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
     a.vout[3 * i + 2] = vz;
 }
 
+// A fused-actuation launch hands the next one its step index through the other slot of the
+// counter pair (the next launch reads that slot; the kernel boundary orders the two).
+__device__ __forceinline__ void advance_step(const StepArgs& a, long long n_step) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.step_out = n_step + 1;
+}
+
 template <bool ACT, bool EXACT, int BATCH, int MODE>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
+    constexpr bool FUSABLE = ACT && MODE != kExplicit;
     const int b = logical_block(a.nblk);
-    if (b >= a.nblk) return;
-    step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b);
+    const long long n_step = FUSABLE && a.fuse ? *a.step_in : 0;
+    if (FUSABLE && a.fuse) advance_step(a, n_step);
+    if (b < a.nblk) step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b, n_step);
 }
 
 // Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
@@ -569,10 +594,13 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
     const int per = (a.nblk + 7) >> 3;
     const int xcd = (int)(blockIdx.x & 7u);
     const int stride = (int)(gridDim.x >> 3);
+    constexpr bool FUSABLE = ACT && MODE != kExplicit;
+    const long long n_step = FUSABLE && a.fuse ? *a.step_in : 0;
+    if (FUSABLE && a.fuse) advance_step(a, n_step);
     for (int j = (int)(blockIdx.x >> 3); j < per; j += stride) {
         const int b = xcd * per + j;
         if (b >= a.nblk) break;
-        step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b);
+        step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b, n_step);
         __syncthreads();  // LDS is restaged for the next block
     }
 }
@@ -599,7 +627,7 @@ __global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, 
         vy = a.vin[3 * own + 1];
         vz = a.vin[3 * own + 2];
     }
-    const long long n0 = *r.step_ctr;
+    const long long n0 = *r.step_in;
     const int2 bg = ACT ? a.blk_groups[0] : make_int2(0, 0);
     const float* fext = a.fext && live ? a.fext + 3 * own : nullptr;
     const int s = t >> 6;
@@ -627,7 +655,7 @@ __global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, 
         a.vout[3 * own + 1] = vy;
         a.vout[3 * own + 2] = vz;
     }
-    if (t == 0) *r.step_ctr = n0 + r.steps;
+    if (t == 0) *r.step_out = n0 + r.steps;
 }
 
 // Total force of eq. (2) + contact normal at the current state (same gather as the step).
@@ -675,28 +703,19 @@ forces_kernel(const float4* __restrict__ xin, const float* __restrict__ mass, co
 // Actuation factors 1 + A_g sin(2 pi f t_n + phi_g) of eq. (2)'s rest lengths at step n, one per
 // (body, group), FP32.  The elapsed fraction of a period, frac(n f dt), is formed exactly in
 // 64-bit fixed point (n * cycles wraps modulo 2^64), so the phase stays accurate to ~1e-7 rad
-// however many steps have been taken.  With `advance`, the last workgroup to finish moves the
-// device step counter on (every workgroup has read it by then).
+// however many steps have been taken.  The step index is n_explicit, or (n_explicit < 0) the
+// device counter *step_in; with `advance`, one thread stores n + 1 to *step_out, the other
+// slot of the counter pair, which the next launch reads.
 __global__ void __launch_bounds__(256)
 actuation_kernel(const float* __restrict__ phase, const float* __restrict__ amp, unsigned long long cycles,
-                 long long* __restrict__ step_ctr, unsigned* __restrict__ done, float* __restrict__ factor,
-                 int n_factor, int advance, long long n_explicit) {
-    const long long n = n_explicit >= 0 ? n_explicit : *step_ctr;
+                 const long long* step_in, long long* step_out, float* __restrict__ factor, int n_factor, int advance,
+                 long long n_explicit) {
+    const long long n = n_explicit >= 0 ? n_explicit : *step_in;
     const float u = period_fraction(n, cycles);
     const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (g < n_factor) factor[g] = actuation_factor(amp[g], phase[g], u);
     else if (g == n_factor) factor[g] = 1.0f;
-    if (advance) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            if (atomicAdd(done, 1u) == gridDim.x - 1) {
-                *step_ctr = n + 1;
-                *done = 0u;
-                __threadfence();
-            }
-        }
-    }
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *step_out = n + 1;
 }
 
 // ---------------------------------------------------------------- FP64 diagnostics
@@ -989,7 +1008,8 @@ inline int grid_for(int64_t nblk) { return (int)(((nblk + 7) / 8) * 8); }
 }  // namespace
 
 hipError_t launch_step(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st) {
-    return launch_step_io(d, d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], nullptr, p, st);
+    return launch_step_io(d, d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], nullptr, p, st, nullptr,
+                          fused_actuation(d) ? 1 : 0, cur);
 }
 
 // Dynamic LDS of one step workgroup: positions, then (table and split modes) the parameter
@@ -1017,13 +1037,17 @@ size_t step_lds_bytes(const DeviceArrays& d) {
     return b;
 }
 
+bool fused_actuation(const DeviceArrays& d) { return d.grp != nullptr && (d.sp_rec || d.narrow || d.packed); }
+
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
-                          float* vstar, const StepParams& p, hipStream_t st, const float* factor) {
+                          float* vstar, const StepParams& p, hipStream_t st, const float* factor, int fuse,
+                          int cur) {
     const int mode = d.sp_rec ? kSplit : d.narrow ? kNarrow : d.packed ? kTable : kExplicit;
+    if (fuse && !fused_actuation(d)) return hipErrorInvalidValue;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
                d.lane_mass, factor ? factor : d.factor, d.fext, vstar, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
                d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
-               d.narrow_tb};
+               d.narrow_tb, fuse, d.phase, d.amp, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), p.cycles};
     const size_t lds = step_lds_bytes(d);
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
@@ -1060,8 +1084,8 @@ hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, 
     StepArgs a{d.x[cur], d.v[cur], d.x[cur ^ 1], d.v[cur ^ 1], d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
                d.lane_mass, d.factor, d.fext, nullptr, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
                d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
-               d.narrow_tb};
-    ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr, steps, dtv0};
+               d.narrow_tb, 0, d.phase, d.amp, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), cycles};
+    ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), steps, dtv0};
     const size_t lds = step_lds_bytes(d);
     const bool act = d.grp != nullptr, ex = p.exact != 0;
     auto go = [&](auto k) { hipLaunchKernelGGL(k, dim3(1), dim3(d.block), lds, st, a, p, r); };
@@ -1091,10 +1115,11 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
 }
 
 hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, int advance, hipStream_t st,
-                            long long n_explicit, float* out) {
+                            long long n_explicit, float* out, int cur) {
     const unsigned grid = (unsigned)((d.n_factor + 1 + 255) / 256);
-    hipLaunchKernelGGL(actuation_kernel, dim3(grid), dim3(256), 0, st, d.phase, d.amp, cycles, d.step_ctr, d.act_done,
-                       out ? out : d.factor, d.n_factor, n_explicit >= 0 ? 0 : advance, n_explicit);
+    hipLaunchKernelGGL(actuation_kernel, dim3(grid), dim3(256), 0, st, d.phase, d.amp, cycles, d.step_ctr + (cur & 1),
+                       d.step_ctr + ((cur & 1) ^ 1), out ? out : d.factor, d.n_factor, n_explicit >= 0 ? 0 : advance,
+                       n_explicit);
     return hipGetLastError();
 }
 

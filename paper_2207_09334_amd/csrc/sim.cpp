@@ -113,7 +113,7 @@ namespace {
 void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
     void* ptrs[] = {d.narrow, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
-                    d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.act_done, d.chunks, d.body_chunk, d.chunk_part,
+                    d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
                     d.body_out, d.fout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -239,8 +239,9 @@ double omega_max(const cronos::Layout& L, const cronos_desc& d, const std::vecto
 }
 
 cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
+    const bool separate = s->actuated && !cronos::fused_actuation(s->d);
     for (int64_t k = 0; k < n; ++k) {
-        if (s->actuated) HIP_TRY(cronos::launch_actuation(s->d, s->cycles, 1, s->stream));
+        if (separate) HIP_TRY(cronos::launch_actuation(s->d, s->cycles, 1, s->stream, -1, nullptr, s->cur));
         HIP_TRY(cronos::launch_step(s->d, s->cur, s->p, s->stream));
         s->cur ^= 1;
     }
@@ -784,10 +785,8 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         TRY(upload(&D.factor, ones.data(), ones.size()));
         TRY(upload(&D.phase, zeros.data(), zeros.size()));
         TRY(upload(&D.amp, zeros.data(), zeros.size()));
-        unsigned zero_u = 0;
-        TRY(upload(&D.act_done, &zero_u, 1));
-        long long zero = 0;
-        TRY(upload(&D.step_ctr, &zero, 1));
+        const long long zeros2[2] = {0, 0};
+        TRY(upload(&D.step_ctr, zeros2, 2));
         TRY(upload(&D.chunks, chunks.data(), chunks.size()));
         TRY(upload(&D.body_chunk, body_chunk.data(), body_chunk.size()));
         TRY(upload<double>(&D.chunk_part, nullptr, chunks.size() * cronos::kDiagFields));
@@ -864,6 +863,7 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
     {
         const double c = freq_hz * sim->dt;
         sim->cycles = (unsigned long long)std::ldexp(c - std::floor(c), 64);
+        sim->p.cycles = sim->cycles;   // the fused step computes its factors from it
     }
     double amax = 0.0;
     for (size_t g = 0; g < m; ++g) amax = std::max(amax, std::fabs(amp[g]));
@@ -973,7 +973,7 @@ extern "C" cronos_status cronos_set_state(cronos_sim sim, const double* x, const
         HIP_TRY(hipMemcpy(sim->d.v[sim->cur], hv.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice));
     }
     long long ctr = step;
-    HIP_TRY(hipMemcpy(sim->d.step_ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sim->d.step_ctr + sim->cur, &ctr, sizeof ctr, hipMemcpyHostToDevice));
     sim->step = step;
     sim->half_kick = sim->verlet;   // Verlet restarts from (x_0, v_0): eq. (5)
     return CRONOS_OK;
@@ -984,7 +984,7 @@ extern "C" cronos_status cronos_eval_forces(cronos_sim sim, double* f) {
     if (!sim || !f) return fail(CRONOS_EINVAL, "eval_forces: NULL argument");
     const int64_t n = sim->d.n;
     HIP_TRY(hipSetDevice(sim->device));
-    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
     HIP_TRY(cronos::launch_forces(sim->d, sim->cur, sim->p, sim->stream));
     if (!sim->h_f) HIP_TRY(hipHostMalloc((void**)&sim->h_f, 3 * n * sizeof(float), 0));
     HIP_TRY(hipMemcpyAsync(sim->h_f, sim->d.fout, 3 * n * sizeof(float), hipMemcpyDeviceToHost, sim->stream));
@@ -1082,7 +1082,7 @@ extern "C" cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_mo
         TRY(alloc(&m.alpha, max_iter));
         TRY(alloc(&m.beta, max_iter));
         HIP_TRY(hipMemsetAsync(m.q[0], 0, 3 * n * sizeof(double), sim->stream));
-        if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
+        if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
         HIP_TRY(cronos::launch_modes_init(sim->d, sim->cur, m, seed, sim->stream));
         std::vector<double> ha(max_iter), hb(max_iter);
         int32_t k = 0, next = std::min<int32_t>(max_iter, std::max<int32_t>(64, 4 * n_modes + 16));
@@ -1130,7 +1130,7 @@ extern "C" cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out) {
     if (!sim || !out) return fail(CRONOS_EINVAL, "diagnostics: NULL argument");
     HIP_TRY(hipSetDevice(sim->device));
     const int nb = sim->nb;
-    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
     HIP_TRY(cronos::launch_diagnostics(sim->d, sim->cur, sim->p, sim->stream));
     if (!sim->h_diag) HIP_TRY(hipHostMalloc((void**)&sim->h_diag, (size_t)nb * cronos::kDiagFields * sizeof(double), 0));
     HIP_TRY(hipMemcpyAsync(sim->h_diag, sim->d.body_out, (size_t)nb * cronos::kDiagFields * sizeof(double),
