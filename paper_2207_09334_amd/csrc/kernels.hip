@@ -920,13 +920,19 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
                   const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
                   const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
                   double2* __restrict__ sens, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
-                  int block, int lds_slots) {
+                  int block, int lds_slots, int stage_factors) {
     extern __shared__ float4 sx[];
     float4* sw = sx + lds_slots;
+    float* sfac = reinterpret_cast<float*>(sw + lds_slots);   // the factor table, when staged
     const int b = logical_block(nblk);
     if (b >= nblk) return;
     const int base = b * block;
     const int t = threadIdx.x;
+    const float* fac = factor;
+    if (ACT && stage_factors) {   // small tables: one LDS copy per workgroup, no dependent global load
+        for (int q = t; q <= n_factor; q += block) sfac[q] = factor[q];
+        fac = sfac;   // visible after the barrier in stage_positions
+    }
     {
         float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
         if (base + t < n) wt = w[base + t];
@@ -970,7 +976,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
         const int lane = t & 63;
         const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
         const int wdt = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
-        constexpr int B = 4;   // entries whose loads are in flight together
+        constexpr int B = 8;   // entries whose loads are in flight together
         int r = 0;
         for (; r + B <= wdt; r += B) {
             int slot[B], g[B];
@@ -986,14 +992,14 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
                 if (ACT) acc[u] = sens[e];
             }
 #pragma unroll
-            for (int u = 0; u < B; ++u) f[u] = ACT ? factor[g[u]] : 1.0f;
+            for (int u = 0; u < B; ++u) f[u] = ACT ? fac[g[u]] : 1.0f;
 #pragma unroll
             for (int u = 0; u < B; ++u) one(e0 + (r + u) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
         }
         for (; r < wdt; ++r) {
             const int e = e0 + r * 64 + lane;
             const int g = ACT ? (int)grp[e] : n_factor;
-            one(e, nbr[e], kl[e], g, ACT ? factor[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
+            one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
         }
     }
     const int i = base + own;
@@ -1004,6 +1010,8 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
 }
 
 inline int grid_for(int64_t nblk) { return (int)(((nblk + 7) / 8) * 8); }
+
+constexpr int kAdjStagedFactors = 4096;
 
 }  // namespace
 
@@ -1164,16 +1172,18 @@ hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float*
 
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
                              double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor) {
-    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4);
     if (!factor) factor = d.factor;
+    // the factor table goes to LDS when small (kAdjStagedFactors entries at most)
+    const int stage = d.grp && d.n_factor + 1 <= kAdjStagedFactors ? 1 : 0;
+    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (stage ? (size_t)(d.n_factor + 1) * sizeof(float) : 0);
     if (d.grp)
         hipLaunchKernelGGL(adj_gather_kernel<true>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
                            d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
-                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
+                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots, stage);
     else
         hipLaunchKernelGGL(adj_gather_kernel<false>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
                            d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
-                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots);
+                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots, stage);
     return hipGetLastError();
 }
 
