@@ -60,6 +60,8 @@ def profile_record(workload: str, launch: dict):
         return None
     if any(rec.get(k) != launch.get(k) for k in ("block_masses", "batch", "persistent_groups", "step_form")):
         return None
+    if rec.get("lanes_per_mass", 1) != launch.get("lanes_per_mass", 1):
+        return None
     return rec
 
 
@@ -101,7 +103,7 @@ def adjoint_bench(args) -> dict:
 
     w = W.quadruped()
     stream = torch.cuda.Stream()
-    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, block_masses=args.block)
+    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, block_masses=args.block, lanes_per_mass=args.lanes)
     v0 = np.zeros_like(x0)
     lw = AG.forward_displacement_weights(lat.mass)
     T, K = args.adjoint_steps, 100
@@ -141,7 +143,8 @@ def adjoint_bench(args) -> dict:
         "data": "synthetic",
         "config": {"workload": w.name, "n_masses": int(lat.n_masses), "n_springs": int(len(lat.ends)),
                    "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph)),
-                   "block_masses": CR.cronos_launch_config(sim)["block_masses"]},
+                   "block_masses": CR.cronos_launch_config(sim)["block_masses"],
+                   "lanes_per_mass": CR.cronos_launch_config(sim)["lanes_per_mass"]},
         "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
         "first_backward_s": first[1],
         "gradient_over_plain_forward": (t_fwd + t_bwd) / t_plain, "loss": loss,
@@ -367,6 +370,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0, help="entries loaded ahead per lane (2, 4 or 8; 0 = default)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per mass (1, 2 or 4; 0 = default)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--fast-diff", action="store_true", help="skip the exact coordinate difference")
     ap.add_argument("--no-table", action="store_true", help="explicit per-entry (k, L0) instead of the table")
@@ -446,7 +450,7 @@ def main(argv=None):
             w = W.cantilever(args.nx, 40, 40)
         lat = PR.build_lattice(w)
         sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
-                              batch=args.batch, tune_steps=20 if args.tune else 0)
+                              batch=args.batch, lanes_per_mass=args.lanes, tune_steps=20 if args.tune else 0)
         n_bodies, batched, actuated = len(w.bodies), len(w.bodies) > 1, w.n_groups > 0
     info = CR.cronos_info(sim)
     launch = CR.cronos_launch_config(sim)
@@ -503,6 +507,7 @@ def main(argv=None):
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
                    "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
                    "exact_difference": not args.fast_diff, "step_form": launch["step_form"],
+                   "lanes_per_mass": launch["lanes_per_mass"],
                    "integrator": args.integrator},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

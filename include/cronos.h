@@ -216,6 +216,12 @@ typedef struct {
     int32_t persistent;           /* 1 = one persistent launch per step (a resident grid walks
                                      the workgroup blocks); 0 = tuned or one workgroup per block;
                                      -1 = force one workgroup per block                       */
+    int32_t lanes_per_mass;       /* lanes sharing each mass's incidence list: 1, 2 or 4
+                                     (workgroups of block_masses * lanes threads, at most 1024;
+                                     compact table forms with one workgroup per block only,
+                                     else 1); 0 = tuned or 1.  More than one lane per mass
+                                     groups each mass's force sum differently (equal to
+                                     rounding, not bitwise, to one lane)                      */
 } cronos_desc;
 
 /* Per-body diagnostics (section "Energy Conservation Tests": elastic, gravitational and
@@ -299,8 +305,8 @@ cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);
 cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
                           int32_t* block_masses, int64_t* step);
 /* Launch configuration in use: masses per workgroup, batch, persistent workgroups (0 = one
- * per block) and the form of the step's incidence data (CRONOS_FORM_*).  Any output may be
- * NULL. */
+ * per block), the form of the step's incidence data (CRONOS_FORM_*) and the lanes per mass.
+ * Any output may be NULL. */
 #define CRONOS_FORM_EXPLICIT 0  /* (slot, k, L0) per entry, every spring evaluated at both ends  */
 #define CRONOS_FORM_TABLE    1  /* 32-bit entries indexing the table of distinct (k, L0) pairs    */
 #define CRONOS_FORM_SPLIT    2  /* spring pass (each spring once per workgroup) + gather pass     */
@@ -308,18 +314,20 @@ cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs,
 #define CRONOS_FORM_NARROW   4  /* table form with 16-bit entries (passive systems whose LDS slot and
                                    pair index fit in 16 bits together): half the entry bytes        */
 cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
-                                   int32_t* step_form);
+                                   int32_t* step_form, int32_t* lanes_per_mass);
 
 /* Launch configuration chosen by the autotuner for a problem. */
 typedef struct {
-    int32_t block_masses, batch, persistent;
+    int32_t block_masses, batch, persistent, lanes_per_mass;
     double us_per_step;           /* measured mean step time of the winner                     */
     double us_default;            /* same for block 256, batch 4, one workgroup per block      */
 } cronos_tune;
 
 /* Autotuner (not in the paper; the step's launch shape).  Creates the simulation of desc
  * once per workgroup size in {128, 256, 512, 1024} and times n_steps steps (after 3 warm-up
- * steps, HIP events on its stream) for every batch in {2, 4, 8} and both launch forms; the
+ * steps, HIP events on its stream) for every batch in {2, 4, 8} and both launch forms with
+ * one lane per mass, and for 2 and 4 lanes per mass (table forms, where the workgroup of
+ * size x lanes threads fits); the
  * fastest configuration is returned and cached for the process under the key (GPU
  * architecture, floor(log2 N), floor(log2 S), actuated, contact), and appended to the file
  * named by the environment variable CRONOS_TUNE_CACHE if set (read back at the first

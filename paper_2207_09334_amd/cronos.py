@@ -55,12 +55,12 @@ class Desc(C.Structure):
                 ("gravity", _f64 * 3), ("damping", _f64), ("dt", _f64), ("ground", _i32),
                 ("ground_z", _f64), ("ground_k", _f64), ("ground_mu", _f64), ("device", _i32),
                 ("stream", _p), ("flags", _u32), ("block_masses", _i32), ("batch", _i32),
-                ("persistent", _i32)]
+                ("persistent", _i32), ("lanes_per_mass", _i32)]
 
 
 class Tune(C.Structure):
-    _fields_ = [("block_masses", _i32), ("batch", _i32), ("persistent", _i32), ("us_per_step", _f64),
-                ("us_default", _f64)]
+    _fields_ = [("block_masses", _i32), ("batch", _i32), ("persistent", _i32), ("lanes_per_mass", _i32),
+                ("us_per_step", _f64), ("us_default", _f64)]
 
 
 class Diag(C.Structure):
@@ -103,7 +103,8 @@ _SIGS = {
     "cronos_get_layout": (C.c_int, [_p] * 6),
     "cronos_candidate_points": (C.c_int, [_p, _i64, _i32, _i32, C.c_uint64, _p]),
     "cronos_cutoff_springs": (C.c_int, [_i64, _p, _f64, _i64, _p, C.POINTER(_i64)]),
-    "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
+                                       C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
     "cronos_rollout": (C.c_int, [_p, _i64, _i32, _p, C.POINTER(_f64)]),
     "cronos_rollout_backward": (C.c_int, [_p, _p, _p, _p, _p]),
@@ -252,7 +253,7 @@ class Sim:
 def cronos_create(x0, mass, ends, k, rest, *, v0=None, pinned=None, grid=None, fext=None, group=None,
                   n_groups=0, body_offset=None, gravity=(0.0, 0.0, -9.81), damping=0.0, dt=1e-4, ground=False,
                   ground_z=0.0, ground_k=0.0, ground_mu=0.0, device=0, stream=None, flags=0,
-                  block_masses=0, batch=0, persistent=0, _tune_steps=0):
+                  block_masses=0, batch=0, persistent=0, lanes_per_mass=0, _tune_steps=0):
     x0 = _arr(x0, np.float64, (-1, 3))
     n = len(x0)
     ends = _arr(ends, np.int32, (-1, 2))
@@ -267,12 +268,12 @@ def cronos_create(x0, mass, ends, k, rest, *, v0=None, pinned=None, grid=None, f
              rest=_ptr(keep["rest"]), group=_ptr(keep["group"]), n_groups=n_groups,
              gravity=(_f64 * 3)(*gravity), damping=damping, dt=dt, ground=int(bool(ground)), ground_z=ground_z,
              ground_k=ground_k, ground_mu=ground_mu, device=device, stream=stream, flags=flags,
-             block_masses=block_masses, batch=batch, persistent=persistent)
+             block_masses=block_masses, batch=batch, persistent=persistent, lanes_per_mass=lanes_per_mass)
     if _tune_steps:
         t = Tune()
         _check(_lib.cronos_autotune(C.byref(d), int(_tune_steps), C.byref(t)))
         return {"block_masses": t.block_masses, "batch": t.batch, "persistent": t.persistent,
-                "us_per_step": t.us_per_step, "us_default": t.us_default}
+                "lanes_per_mass": t.lanes_per_mass, "us_per_step": t.us_per_step, "us_default": t.us_default}
     h = _p()
     _check(_lib.cronos_create(C.byref(d), C.byref(h)))
     return Sim(h, n, len(ends), nb, n_groups)
@@ -305,9 +306,10 @@ def cronos_cutoff_springs(points, cutoff: float) -> np.ndarray:
 
 
 def cronos_launch_config(sim: Sim) -> dict:
-    b, bt, pg, fm = _i32(), _i32(), _i32(), _i32()
-    _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg), C.byref(fm)))
-    return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value, "step_form": FORMS[fm.value]}
+    b, bt, pg, fm, ln = _i32(), _i32(), _i32(), _i32(), _i32()
+    _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg), C.byref(fm), C.byref(ln)))
+    return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value, "step_form": FORMS[fm.value],
+            "lanes_per_mass": ln.value}
 
 
 def cronos_destroy(sim: Sim):

@@ -586,6 +586,122 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     if (b < a.nblk) step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b, n_step);
 }
 
+// Several lanes per mass (LPM = 2 or 4; compact table forms): lane j of a mass's group walks its
+// incidence rows j, j + LPM, ... and the groups' partial sums are combined by a fixed pairing
+// of cross-lane exchanges (the same value in every lane of the group).  More wavefronts for
+// the same masses, each with a shorter dependent chain: for bodies too small to fill the chip.
+// The sum is grouped differently from the one-lane form, so the two agree to rounding only.
+template <bool ACT, int EX, int LPM, bool NARROW>
+__device__ __forceinline__ void gather_lanes(uint32_t tbase, const float* __restrict__ sf, float4 xi, int s, int sub,
+                                             int nslice, const int32_t* __restrict__ slice_ptr,
+                                             const uint32_t* __restrict__ packed, const uint16_t* __restrict__ narrow,
+                                             int tb, float& fx, float& fy, float& fz) {
+    fx = fy = fz = 0.0f;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s < nslice) {
+        const int lane = ((int)threadIdx.x / LPM) & 63;
+        const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
+        const int w = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
+        const int rows = (w + LPM - 1) / LPM;
+        const uint32_t tmask = (1u << tb) - 1u;
+        auto one = [&](uint32_t q) {
+            uint32_t xa, ca, gi = 0;
+            if (NARROW) {
+                xa = (q >> tb) << 4;
+                ca = ((q & tmask) << 4) | tbase;
+            } else {
+                decode_entry<ACT>(q, tbase, xa, ca, gi);
+            }
+            const float4 xj = lds_f4(xa);
+            const float4 c = lds_f4(ca);
+            const float g = ACT ? sf[gi] : 1.0f;
+            float dx, dy, dz;
+            const float fac = hooke_fac_tab<ACT, EX>(xi, xj, c, g, dx, dy, dz);
+            fx = __builtin_fmaf(fac, dx, fx);
+            fy = __builtin_fmaf(fac, dy, fy);
+            fz = __builtin_fmaf(fac, dz, fz);
+        };
+        constexpr int B = 2;
+        for (int k = 0; k < rows; k += B) {
+            uint32_t q[B];
+            bool ok[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int r = (k + u) * LPM + sub;
+                ok[u] = r < w;
+                const int e = e0 + r * 64 + lane;
+                q[u] = ok[u] ? (NARROW ? (uint32_t)narrow[e] : packed[e]) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (ok[u]) one(q[u]);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < LPM; o <<= 1) {
+        fx += __shfl_xor(fx, o, 64);
+        fy += __shfl_xor(fy, o, 64);
+        fz += __shfl_xor(fz, o, 64);
+    }
+}
+
+// One step with LPM lanes per mass: a workgroup of block * LPM threads stages its block's
+// positions and halo, thread t serves mass lane t / LPM; the first lane of each mass
+// integrates.  Compact table forms (32- or 16-bit entries), one workgroup per block.
+template <bool ACT, bool EXACT, int LPM, bool NARROW>
+__global__ void __launch_bounds__(1024) step_lanes_kernel(StepArgs a, StepParams p) {
+    extern __shared__ float4 sx[];
+    const int b = logical_block(a.nblk);
+    const long long n_step = ACT && a.fuse ? *a.step_in : 0;
+    if (ACT && a.fuse) advance_step(a, n_step);
+    if (b >= a.nblk) return;
+    const int t = (int)threadIdx.x, nt = (int)blockDim.x;
+    const int m = t / LPM, sub = t % LPM;
+    const int base = b * a.block;
+    const uint32_t tbase = table_base(a.lds_slots);
+    float4* st = reinterpret_cast<float4*>(reinterpret_cast<char*>(sx) + tbase);
+    float* sf = reinterpret_cast<float*>(st + a.n_table);
+    for (int q = t; q < a.n_table; q += nt) st[q] = a.table[q];
+    if (ACT) {
+        const int2 bg = a.blk_groups[b];
+        if (a.fuse) {
+            const float u = period_fraction(n_step, a.cycles);
+            for (int q = t; q <= bg.y; q += nt)
+                sf[q] = q ? actuation_factor(a.amp[bg.x + q - 1], a.phase[bg.x + q - 1], u) : 1.0f;
+        } else {
+            for (int q = t; q <= bg.y; q += nt) sf[q] = q ? a.factor[bg.x + q - 1] : 1.0f;
+        }
+    }
+    for (int q = t; q < a.block; q += nt) sx[q] = base + q < a.n ? a.xin[base + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int h0 = a.halo_ptr[b], h1 = a.halo_ptr[b + 1];
+    for (int h = h0 + t; h < h1; h += nt) sx[a.block + (h - h0)] = a.xin[a.halo_idx[h]];
+    __syncthreads();
+    const int own = a.lane_mass[base + m];
+    const float4 xi = sx[own];
+    const int s = (base + m) >> 6;
+    float fx, fy, fz;
+    const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
+    if (mode == kPlain)
+        gather_lanes<ACT, kPlain, LPM, NARROW>(tbase, sf, xi, s, sub, a.nslice, a.slice_ptr, a.packed, a.narrow,
+                                               a.narrow_tb, fx, fy, fz);
+    else if (mode == kExactZ)
+        gather_lanes<ACT, kExactZ, LPM, NARROW>(tbase, sf, xi, s, sub, a.nslice, a.slice_ptr, a.packed, a.narrow,
+                                                a.narrow_tb, fx, fy, fz);
+    else
+        gather_lanes<ACT, kExactAll, LPM, NARROW>(tbase, sf, xi, s, sub, a.nslice, a.slice_ptr, a.packed, a.narrow,
+                                                  a.narrow_tb, fx, fy, fz);
+    const int i = base + own;
+    if (sub != 0 || i >= a.n) return;
+    float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
+    float4 xo;
+    integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+              a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+    a.xout[i] = xo;
+    a.vout[3 * i + 0] = vx;
+    a.vout[3 * i + 1] = vy;
+    a.vout[3 * i + 2] = vz;
+}
+
 // Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
 // on XCD w % 8 and takes that XCD's contiguous eighth of the blocks in strides.
 template <bool ACT, bool EXACT, int BATCH, int MODE>
@@ -1026,7 +1142,9 @@ hipError_t step_static_lds(size_t* bytes) {
     const void* ks[] = {(const void*)step_kernel<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kTable>,
                         (const void*)step_persistent<false, true, 4, kTable>, (const void*)step_kernel<true, true, 4, kSplit>,
                         (const void*)step_persistent<true, false, 8, kSplit>,
-                        (const void*)step_kernel<false, true, 4, kNarrow>};
+                        (const void*)step_kernel<false, true, 4, kNarrow>,
+                        (const void*)step_lanes_kernel<true, true, 4, false>,
+                        (const void*)step_lanes_kernel<false, true, 2, true>};
     *bytes = 0;
     for (const void* k : ks) {
         hipFuncAttributes at{};
@@ -1057,6 +1175,21 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
                d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
                d.narrow_tb, fuse, d.phase, d.amp, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), p.cycles};
     const size_t lds = step_lds_bytes(d);
+    if (d.lanes > 1 && (mode == kTable || mode == kNarrow)) {
+        const bool act = d.grp != nullptr, ex = p.exact != 0, nar = mode == kNarrow && !act;
+        const dim3 g((unsigned)grid_for(d.nblk)), th((unsigned)(d.block * d.lanes));
+        auto go = [&](auto k) { hipLaunchKernelGGL(k, g, th, lds, st, a, p); };
+        if (d.lanes == 2) {
+            if (act) ex ? go(step_lanes_kernel<true, true, 2, false>) : go(step_lanes_kernel<true, false, 2, false>);
+            else if (nar) ex ? go(step_lanes_kernel<false, true, 2, true>) : go(step_lanes_kernel<false, false, 2, true>);
+            else ex ? go(step_lanes_kernel<false, true, 2, false>) : go(step_lanes_kernel<false, false, 2, false>);
+        } else {
+            if (act) ex ? go(step_lanes_kernel<true, true, 4, false>) : go(step_lanes_kernel<true, false, 4, false>);
+            else if (nar) ex ? go(step_lanes_kernel<false, true, 4, true>) : go(step_lanes_kernel<false, false, 4, true>);
+            else ex ? go(step_lanes_kernel<false, true, 4, false>) : go(step_lanes_kernel<false, false, 4, false>);
+        }
+        return hipGetLastError();
+    }
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
     auto go = [&](auto normal, auto pers) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -300,7 +301,8 @@ void load_tune_cache_locked() {
     std::ifstream f(path);
     std::string key;
     cronos_tune t{};
-    while (f >> key >> t.block_masses >> t.batch >> t.persistent >> t.us_per_step >> t.us_default) g_tune[key] = t;
+    while (f >> key >> t.block_masses >> t.batch >> t.persistent >> t.lanes_per_mass >> t.us_per_step >> t.us_default)
+        g_tune[key] = t;
 }
 
 bool lookup_tune(const std::string& key, cronos_tune* t) {
@@ -320,8 +322,8 @@ void store_tune(const std::string& key, const cronos_tune& t) {
     g_tune[key] = t;
     if (const char* path = std::getenv("CRONOS_TUNE_CACHE")) {
         std::ofstream f(path, std::ios::app);
-        f << key << " " << t.block_masses << " " << t.batch << " " << t.persistent << " " << t.us_per_step << " "
-          << t.us_default << "\n";
+        f << key << " " << t.block_masses << " " << t.batch << " " << t.persistent << " " << t.lanes_per_mass << " "
+          << t.us_per_step << " " << t.us_default << "\n";
     }
 }
 
@@ -361,19 +363,26 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     if (d->batch != 0 && d->batch != 2 && d->batch != 4 && d->batch != 8)
         return fail(CRONOS_EINVAL, "create: batch must be 0, 2, 4 or 8");
     if (d->persistent < -1 || d->persistent > 1) return fail(CRONOS_EINVAL, "create: persistent must be -1, 0 or 1");
+    if (d->lanes_per_mass != 0 && d->lanes_per_mass != 1 && d->lanes_per_mass != 2 && d->lanes_per_mass != 4)
+        return fail(CRONOS_EINVAL, "create: lanes_per_mass must be 0, 1, 2 or 4");
 
     // launch configuration: explicit values win, then a cached tuning result, then defaults
-    int32_t block = d->block_masses, batch = d->batch, persistent = d->persistent;
-    if (block == 0 || batch == 0 || persistent == 0) {
+    int32_t block = d->block_masses, batch = d->batch, persistent = d->persistent, lanes = d->lanes_per_mass;
+    if (block == 0 || batch == 0 || persistent == 0 || lanes == 0) {
         cronos_tune t{};
         if (d->n_masses >= 1 && lookup_tune(tune_key(*d), &t)) {
             if (block == 0) block = t.block_masses;
             if (batch == 0) batch = t.batch;
             if (persistent == 0) persistent = t.persistent;
+            if (lanes == 0) lanes = t.lanes_per_mass;
         }
     }
     if (batch == 0) batch = 4;
     if (persistent < 0) persistent = 0;
+    if (lanes < 1) lanes = 1;
+    if (lanes > 1 && block != 0 && block * lanes > 1024)
+        return fail(CRONOS_EINVAL, "create: block_masses * lanes_per_mass must be at most 1024");
+    if (lanes > 1 && block == 0) block = 1024 / lanes < 256 ? 1024 / lanes : 256;
     // the resident form holds the whole system in one workgroup
     if ((d->flags & CRONOS_RESIDENT) && n <= 1024 && (block == 0 || block < n))
         block = (int32_t)std::max<int64_t>(cronos::kSlice, (n + cronos::kSlice - 1) / cronos::kSlice * cronos::kSlice);
@@ -699,6 +708,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     D.lds_slots = L.block + L.max_halo;
     D.nb = sim->nb;
     D.batch = batch;
+    D.lanes = lanes;
     D.n_factor = n_factor;
     D.n_chunks = (int32_t)chunks.size();
     if (hipSetDevice(d->device) != hipSuccess) {
@@ -818,6 +828,9 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     P.ox = sim->origin[0];
     P.oy = sim->origin[1];
     P.oz = sim->origin[2];
+    // several lanes per mass exist for the compact table forms, one workgroup per block
+    if (D.lanes > 1 && (D.resident || D.sp_rec || !(D.packed || D.narrow))) D.lanes = 1;
+    if (D.lanes > 1) persistent = 0;
     if (persistent > 0) {
         int g = 0;
         hipError_t e = cronos::persistent_grid(D, P.exact, &g);
@@ -1375,11 +1388,13 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
 }
 
 extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch,
-                                              int32_t* persistent_groups, int32_t* step_form) {
+                                              int32_t* persistent_groups, int32_t* step_form,
+                                              int32_t* lanes_per_mass) {
     if (!sim) return fail(CRONOS_EINVAL, "launch_config: NULL handle");
     if (block_masses) *block_masses = sim->lay.block;
     if (batch) *batch = sim->d.batch;
     if (persistent_groups) *persistent_groups = sim->d.persistent_groups;
+    if (lanes_per_mass) *lanes_per_mass = sim->d.lanes;
     if (step_form)
         *step_form = sim->d.resident ? CRONOS_FORM_RESIDENT
                      : sim->d.sp_rec ? CRONOS_FORM_SPLIT
@@ -1402,6 +1417,7 @@ extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, 
         dd.block_masses = blk;
         dd.batch = 4;
         dd.persistent = -1;
+        dd.lanes_per_mass = 1;
         dd.flags |= CRONOS_ALLOW_UNSTABLE;   // checked once by the caller's own create
         cronos_sim sim = nullptr;
         cronos_status st = cronos_create(&dd, &sim);
@@ -1414,11 +1430,21 @@ extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, 
         }
         int pgrid = 0;
         if (cronos::persistent_grid(sim->d, sim->p.exact, &pgrid) != hipSuccess) pgrid = 0;
-        for (int bt : batches) {
-            for (int pers = 0; pers < 2; ++pers) {
-                if (pers && pgrid <= 0) continue;
+        // configurations: (batch, persistent) with one lane per mass, then 2 and 4 lanes per
+        // mass (table forms, one workgroup per block; batch does not apply)
+        const bool lanes_ok = !sim->d.resident && !sim->d.sp_rec && (sim->d.packed || sim->d.narrow);
+        std::vector<std::array<int, 3>> cfgs;
+        for (int bt : batches)
+            for (int pers = 0; pers < 2; ++pers)
+                if (!pers || pgrid > 0) cfgs.push_back({bt, pers, 1});
+        for (int ln : {2, 4})
+            if (lanes_ok && blk * ln <= 1024) cfgs.push_back({4, 0, ln});
+        for (const auto& cfg : cfgs) {
+            const int bt = cfg[0], pers = cfg[1], ln = cfg[2];
+            {
                 sim->d.batch = bt;
                 sim->d.persistent_groups = pers ? pgrid : 0;
+                sim->d.lanes = ln;
                 sim->use_graph = false;
                 // warm up and time on the simulation's stream; the state evolves, which is
                 // harmless for timing (the tuner's simulation is discarded)
@@ -1436,12 +1462,13 @@ extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, 
                     return s2 == CRONOS_EDEVICE ? fail(CRONOS_EDEVICE, "autotune: timing failed") : s2;
                 }
                 const double us = 1e3 * (double)ms / n_steps;
-                if (blk == 256 && bt == 4 && !pers) best.us_default = us;
+                if (blk == 256 && bt == 4 && !pers && ln == 1) best.us_default = us;
                 if (us < best.us_per_step) {
                     best.us_per_step = us;
                     best.block_masses = blk;
                     best.batch = bt;
                     best.persistent = pers;
+                    best.lanes_per_mass = ln;
                 }
             }
         }

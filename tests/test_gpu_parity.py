@@ -12,7 +12,7 @@ from oracle import diagnostics as D
 from oracle import physics as P
 from paper_2207_09334_amd import cronos as CR
 from paper_2207_09334_amd import problem as PR
-from tests.gpu_common import force_error, oracle_problem, position_error, say
+from tests.gpu_common import as_f32, force_error, force_scale, oracle_problem, position_error, say
 
 pytestmark = pytest.mark.gpu
 
@@ -20,12 +20,12 @@ F_TOL = 1e-5
 X_TOL = 1e-4
 
 
-def _run_pair(w, steps, every=100, x0=None, v0=None, start=0, flags=CR.CHECK_LAYOUT):
+def _run_pair(w, steps, every=100, x0=None, v0=None, start=0, flags=CR.CHECK_LAYOUT, **create):
     """Run the oracle and the device from the same inputs; return the worst position error."""
     lat, sys_, ox0 = oracle_problem(w)
     x0 = ox0 if x0 is None else x0
     v0 = np.zeros_like(x0) if v0 is None else v0
-    sim, nlat, _ = PR.create(w, x0=x0, v0=v0, flags=flags)
+    sim, nlat, _ = PR.create(w, x0=x0, v0=v0, flags=flags, **create)
     if start:
         CR.cronos_set_state(sim, x0, v0, start)
     x, v = x0.copy(), v0.copy()
@@ -417,3 +417,73 @@ def test_resident_form_matches_oracle_cube_1000():
 def test_resident_flag_ignored_for_large_systems():
     sim, _, _ = PR.create(W.cantilever(40, 8, 8), flags=CR.RESIDENT)
     assert CR.cronos_launch_config(sim)["step_form"] == "narrow"
+
+
+# ------------------------------------------------------------------------- lanes per mass
+
+def test_lanes_per_mass_forces_and_positions():
+    """Two and four lanes per mass (the table forms; each mass's sum grouped by lane).  Forces:
+    one step from rest at a deformed state (no contact, no damping) gives v' = dt F/m with F
+    the total force of eq. (2) (springs and gravity), so the step's own F is m v'/dt; within
+    the 1e-5 bar of the oracle's on the actuated quadruped and the passive cantilever slab.  Positions: within 1e-4 of the bbox over 1000
+    steps of the cube drop (contact, friction, damping)."""
+    say("case: lanes per mass 2 and 4: quadruped / cantilever step forces, cube drop positions")
+    for w, over in ((W.quadruped(), dict(ground=False, damping=0.0)), (W.cantilever(60, 10, 10), {})):
+        lat, _, x0 = oracle_problem(w)
+        sys_ = P.system_from(lat, w, **over)
+        free = ~np.asarray(lat.pinned, bool)
+        inv_m = (1.0 / lat.mass).astype(np.float32).astype(np.float64)
+        dt32 = float(np.float32(w.dt))
+        for lanes in (2, 4):
+            sim, _, _ = PR.create(w, x0=x0, lanes_per_mass=lanes, block_masses=256 if lanes == 2 else 128, **over)
+            cfg = CR.cronos_launch_config(sim)
+            assert cfg["lanes_per_mass"] == lanes and cfg["step_form"] in ("table", "narrow")
+            CR.cronos_step(sim, 150)
+            xg, _, n = CR.cronos_read_state(sim)
+            CR.cronos_set_state(sim, xg, np.zeros_like(xg), n)
+            CR.cronos_step(sim, 1)
+            _, v1, _ = CR.cronos_read_state(sim)
+            f_dev = (v1 / dt32) / inv_m[:, None]
+            s32 = as_f32(sys_)
+            f_ref = P.forces(s32, xg, n * w.dt)
+            S = force_scale(s32, xg, n * w.dt)
+            e = float((np.linalg.norm(f_dev - f_ref, axis=1) / S)[free].max())
+            say(f"  {w.name} lanes {lanes}: step force err {e:.3e}")
+            assert e <= F_TOL
+            sim.close()
+    w = W.cube_drop()
+    for lanes in (2, 4):
+        worst, sim, *_ = _run_pair(w, 1000, lanes_per_mass=lanes)
+        say(f"  cube drop lanes {lanes}: position err {worst:.3e}")
+        assert CR.cronos_launch_config(sim)["lanes_per_mass"] == lanes
+        assert worst <= X_TOL
+
+
+def test_lanes_per_mass_repeatable_and_block_independent():
+    """For a fixed number of lanes per mass the states are bitwise repeatable and do not depend
+    on the workgroup size; the step counter and the actuation factors inside the step follow
+    the one-lane form's (positions agree to rounding)."""
+    w = W.quadruped()
+    say("case: lanes per mass 4, quadruped 300 steps: repeat, blocks 64 / 128 / 256")
+    outs = []
+    for blk in (128, 128, 64, 256):
+        sim, _, _ = PR.create(w, lanes_per_mass=4, block_masses=blk)
+        CR.cronos_step(sim, 300)
+        xg, vg, n = CR.cronos_read_state(sim)
+        assert n == 300
+        outs.append((xg, vg))
+        sim.close()
+    for xg, vg in outs[1:]:
+        assert np.array_equal(xg, outs[0][0]) and np.array_equal(vg, outs[0][1])
+    ref, _, _ = PR.create(w, lanes_per_mass=1)
+    CR.cronos_step(ref, 300)
+    x1, _, _ = CR.cronos_read_state(ref)
+    assert position_error(outs[0][0], x1) <= X_TOL
+
+
+def test_lanes_per_mass_bad_values():
+    w = W.cube_drop()
+    with pytest.raises(CR.CronosError):
+        PR.create(w, lanes_per_mass=3)
+    with pytest.raises(CR.CronosError):
+        PR.create(w, lanes_per_mass=4, block_masses=512)
