@@ -103,7 +103,10 @@ def adjoint_bench(args) -> dict:
 
     w = W.quadruped()
     stream = torch.cuda.Stream()
-    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, block_masses=args.block, lanes_per_mass=args.lanes)
+    # the launch shape (workgroup size, batch, lanes per mass) from the autotuner unless given
+    tune = 0 if (args.block or args.lanes) else 20
+    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, block_masses=args.block, lanes_per_mass=args.lanes,
+                             tune_steps=tune)
     v0 = np.zeros_like(x0)
     lw = AG.forward_displacement_weights(lat.mass)
     T, K = args.adjoint_steps, 100
@@ -144,7 +147,8 @@ def adjoint_bench(args) -> dict:
         "config": {"workload": w.name, "n_masses": int(lat.n_masses), "n_springs": int(len(lat.ends)),
                    "steps": T, "checkpoint_every": K, "parameters": int(2 * len(ph)),
                    "block_masses": CR.cronos_launch_config(sim)["block_masses"],
-                   "lanes_per_mass": CR.cronos_launch_config(sim)["lanes_per_mass"]},
+                   "lanes_per_mass": CR.cronos_launch_config(sim)["lanes_per_mass"],
+                   "batch": CR.cronos_launch_config(sim)["batch"], "autotuned": bool(tune)},
         "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
         "first_backward_s": first[1],
         "gradient_over_plain_forward": (t_fwd + t_bwd) / t_plain, "loss": loss,

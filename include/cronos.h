@@ -324,7 +324,7 @@ typedef struct {
 } cronos_tune;
 
 /* Autotuner (not in the paper; the step's launch shape).  Creates the simulation of desc
- * once per workgroup size in {128, 256, 512, 1024} and times n_steps steps (after 3 warm-up
+ * once per workgroup size in {64, 128, 256, 512, 1024} and times n_steps steps (after 3 warm-up
  * steps, HIP events on its stream) for every batch in {2, 4, 8} and both launch forms with
  * one lane per mass, and for 2 and 4 lanes per mass (table forms, where the workgroup of
  * size x lanes threads fits); the

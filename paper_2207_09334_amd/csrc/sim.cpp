@@ -1410,7 +1410,7 @@ extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, 
     cronos_tune best{};
     best.us_per_step = 1e300;
     best.us_default = 0.0;
-    const int blocks[] = {128, 256, 512, 1024};
+    const int blocks[] = {64, 128, 256, 512, 1024};
     const int batches[] = {2, 4, 8};
     for (int blk : blocks) {
         cronos_desc dd = *d;
