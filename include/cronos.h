@@ -210,7 +210,8 @@ typedef struct {
     uint32_t flags;               /* CRONOS_* flags                                           */
     int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = the
                                      tuned value for this problem class if one is cached (see
-                                     cronos_autotune), else 256                               */
+                                     cronos_autotune), else 512 for a passive system of at least
+                                     131,072 masses and 256 otherwise                         */
     int32_t batch;                /* incidence entries each lane keeps in flight: 2, 4 or 8;
                                      0 = tuned or 4                                           */
     int32_t persistent;           /* 1 = one persistent launch per step (a resident grid walks
