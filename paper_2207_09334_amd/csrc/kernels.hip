@@ -1,23 +1,25 @@
 // Device kernels of the mass-spring step for gfx950 (CDNA4, wave64).
 //
-// One time step is one launch of `step_kernel` (plus a launch that tabulates the actuation
-// factors when springs are actuated).  It fuses what Algorithm 1 splits into a spring pass
-// and a mass pass: every lane owns one mass, walks that mass's incidence list in a fixed
-// order and sums the eq. (2) spring forces itself, so no force is ever written twice and no
-// atomic is needed; the sum is bitwise reproducible run to run.
+// One time step is one launch of `step_kernel` (actuated bodies in the compact table forms
+// compute their actuation factors inside it; the explicit form takes a separate actuation
+// launch).  It fuses what Algorithm 1 splits into a spring pass and a mass pass: every lane
+// owns one mass (or 2 or 4 lanes share one, `step_lanes_kernel`), walks that mass's incidence
+// list in a fixed order and sums the eq. (2) spring forces itself, so no force is ever written
+// twice and no atomic is needed; the sum is bitwise reproducible run to run.
 //
 // Memory: positions are float4 (x, y, z, 1/m) so one 16-byte load fetches a neighbour; a
 // workgroup first copies its own masses and its halo (the neighbours outside the workgroup)
 // into LDS, then every incidence reads its neighbour from LDS.  The incidence stream is laid
-// out column-major per 64-mass slice, so each wavefront's loads are contiguous; in its
-// compact form an entry is one 32-bit word (neighbour slot, index into the LDS table of
-// distinct (k, L0) pairs, actuation factor).  Workgroups are spread so that each of the 8
-// XCDs gets a contiguous range of the Morton order (their halos then overlap within one L2).
+// out column-major per 64-mass slice, so each wavefront's loads are contiguous; in the compact
+// forms an entry is one 16-bit word (passive bodies: neighbour slot and index into the LDS
+// table of distinct (k, L0) pairs) or one 32-bit word (also the actuation factor).
+// Workgroups are spread so that each of the 8 XCDs gets a contiguous range of the Morton
+// order (their halos then overlap within one L2).
 //
 // Precision: FP32 state and FP32 accumulation.  The elongation |d| - L0 of a nearly relaxed
 // spring is a difference of nearly equal numbers; it is computed as (|d|^2 - L0^2)/(|d| + L0)
-// with |d|^2 - L0^2 formed from error-free products (FMA) and error-free sums (Fast2Sum on
-// the sorted squares), so its error is a few ulps of the elongation itself, not of L0.
+// with |d|^2 - L0^2 formed in FP64 from the FP32 differences (exact squares, L0^2 held
+// exactly), so its error is about an ulp of the elongation itself, not of L0.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
