@@ -222,7 +222,8 @@ typedef struct {
                                      compact table forms with one workgroup per block only,
                                      else 1); 0 = tuned or 1.  More than one lane per mass
                                      groups each mass's force sum differently (equal to
-                                     rounding, not bitwise, to one lane)                      */
+                                     rounding, not bitwise, to one lane).  A tuned value is
+                                     taken only when block_masses is 0 as well               */
 } cronos_desc;
 
 /* Per-body diagnostics (section "Energy Conservation Tests": elastic, gravitational and

@@ -371,10 +371,11 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     if (block == 0 || batch == 0 || persistent == 0 || lanes == 0) {
         cronos_tune t{};
         if (d->n_masses >= 1 && lookup_tune(tune_key(*d), &t)) {
+            // lanes per mass were tuned together with the workgroup size: taken only with it
+            if (lanes == 0 && block == 0) lanes = t.lanes_per_mass;
             if (block == 0) block = t.block_masses;
             if (batch == 0) batch = t.batch;
             if (persistent == 0) persistent = t.persistent;
-            if (lanes == 0) lanes = t.lanes_per_mass;
         }
     }
     if (batch == 0) batch = 4;

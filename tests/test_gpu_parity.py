@@ -487,3 +487,28 @@ def test_lanes_per_mass_bad_values():
         PR.create(w, lanes_per_mass=3)
     with pytest.raises(CR.CronosError):
         PR.create(w, lanes_per_mass=4, block_masses=512)
+
+
+def test_autotuner_picks_a_valid_shape_and_later_creates_use_it():
+    """The autotuner times workgroup size x batch x launch form x lanes per mass on the problem
+    and caches the fastest for its problem class: a later create that gives no launch values
+    gets it, explicit values still win, and the tuned simulation matches the oracle."""
+    w = W.quadruped()
+    say("case: autotuner on the quadruped (5 steps per configuration)")
+    sim, _, _ = PR.create(w, tune_steps=5)
+    cfg = CR.cronos_launch_config(sim)
+    say(f"  tuned: {cfg}")
+    assert cfg["block_masses"] in (64, 128, 256, 512, 1024)
+    assert cfg["lanes_per_mass"] in (1, 2, 4) and cfg["block_masses"] * cfg["lanes_per_mass"] <= 1024
+    assert cfg["batch"] in (2, 4, 8)
+    again, _, _ = PR.create(w)
+    assert CR.cronos_launch_config(again) == cfg
+    explicit, _, _ = PR.create(w, block_masses=256, lanes_per_mass=1, batch=4, persistent=-1)
+    e = CR.cronos_launch_config(explicit)
+    assert (e["block_masses"], e["lanes_per_mass"], e["batch"], e["persistent_groups"]) == (256, 1, 4, 0)
+    lat, sys_, x0 = oracle_problem(w)
+    CR.cronos_set_state(again, x0, np.zeros_like(x0), 0)
+    CR.cronos_step(again, 100)
+    xg, _, _ = CR.cronos_read_state(again)
+    xr, _ = P.run(sys_, x0, np.zeros_like(x0), 0, 100)
+    assert position_error(xg, xr) <= X_TOL
