@@ -42,6 +42,15 @@ def stiffness(x: np.ndarray, ends: np.ndarray, k: np.ndarray, l0: np.ndarray) ->
     return sp.csr_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))), shape=(3 * N, 3 * N))
 
 
+def contact_stiffness(x: np.ndarray, ground_z: float, ground_k: float) -> sp.csr_matrix:
+    """Tangent stiffness of the penalty contact plane (Appendix A's contact planes, normal force
+    k_g max(0, z_g - z) on +z): k_g on the z diagonal of every mass below the plane."""
+    N = len(x)
+    d = np.zeros(3 * N)
+    d[2::3] = np.where(x[:, 2] < ground_z, ground_k, 0.0)
+    return sp.diags(d).tocsr()
+
+
 def free_dofs(pinned: np.ndarray) -> np.ndarray:
     return np.nonzero(np.repeat(~np.asarray(pinned, bool), 3))[0]
 
@@ -55,10 +64,13 @@ def static_displacement(x, ends, k, l0, pinned, f) -> np.ndarray:
     return u.reshape(-1, 3)
 
 
-def natural_frequencies(x, ends, k, l0, mass, pinned, count: int = 2):
+def natural_frequencies(x, ends, k, l0, mass, pinned, count: int = 2, ground=None):
     """Smallest ``count`` angular frequencies w (rad/s) and mode shapes of K v = w^2 M v,
-    found by shift-invert Lanczos around zero (a sparse factorisation of K)."""
+    found by shift-invert Lanczos around zero (a sparse factorisation of K).  ground =
+    (z_g, k_g) adds the contact plane's stiffness to K."""
     K = stiffness(x, ends, k, l0)
+    if ground is not None:
+        K = (K + contact_stiffness(x, ground[0], ground[1])).tocsr()
     dof = free_dofs(pinned)
     Kf = K[dof][:, dof].tocsc()
     Mf = sp.diags(np.repeat(mass, 3)[dof]).tocsc()

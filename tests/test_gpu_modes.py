@@ -93,3 +93,22 @@ def test_bad_arguments():
     for kw in (dict(n_modes=0), dict(n_modes=33), dict(tol=0.0), dict(tol=1.5), dict(n_modes=4, max_iter=10)):
         with pytest.raises(CR.CronosError):
             CR.cronos_natural_frequencies(sim, **kw)
+
+
+def test_contact_plane_stiffness_enters():
+    """A 61x7x5 cantilever whose bottom layer sits 2 mm below a contact plane: the plane's
+    penalty stiffness k_g on those masses' z enters K (the oracle's K + contact term at the
+    device's positions), and raises the frequencies above the free beam's."""
+    w = W.cantilever(61, 7, 5)
+    lat = L.build(w)
+    over = dict(gravity=(0.0, 0.0, 0.0), ground=True, ground_z=0.002, ground_k=2.0e3, ground_mu=0.0)
+    sim, _, _ = PR.create(w, x0=lat.x, **over)
+    xg, _, _ = CR.cronos_read_state(sim)
+    assert (xg[:, 2] < 0.002).sum() > 0
+    om, _ = LN.natural_frequencies(xg, lat.ends, F32(lat.k), F32(lat.rest), F32(lat.mass), lat.pinned, 3,
+                                   ground=(float(np.float32(0.002)), float(np.float32(2.0e3))))
+    free = oracle_omegas(lat, xg, 3)
+    dev, iters = CR.cronos_natural_frequencies(sim, n_modes=3, tol=1e-10)
+    say(f"  on the plane: device {dev} ({iters} steps); oracle {om}; without the plane {free}")
+    assert dev == pytest.approx(om, rel=1e-7)
+    assert om[0] > 1.01 * free[0]

@@ -113,3 +113,23 @@ def test_stiffness_matches_force_derivative():
     fp = P.spring_forces(x + h * du, lat.ends, lat.k, l0)
     fm = P.spring_forces(x - h * du, lat.ends, lat.k, l0)
     np.testing.assert_allclose(-(fp - fm).ravel() / (2 * h), K @ du.ravel(), rtol=1e-5, atol=1e-6)
+
+
+def test_contact_stiffness_matches_force_derivative():
+    """The contact plane's tangent stiffness is the derivative of the penalty normal force:
+    central differences of the oracle's total force with the plane on, at a state where part
+    of the body is below the plane (kept away from the kink at z = z_g)."""
+    w = W.cube_drop(3)
+    lat = L.build(w)
+    sys_ = P.system_from(lat, w, gravity=np.zeros(3))
+    rng = np.random.default_rng(9)
+    x = lat.x.copy()
+    x[:, 2] += sys_.ground_z - x[:, 2].min() - 0.5 * lat.rest.min()     # the bottom layer 1/2 spacing under
+    x += rng.uniform(-1e-4, 1e-4, x.shape)
+    below = x[:, 2] < sys_.ground_z
+    assert 0 < below.sum() < len(x)
+    K = (LN.stiffness(x, lat.ends, lat.k, lat.rest) + LN.contact_stiffness(x, sys_.ground_z, sys_.ground_k)).toarray()
+    du = rng.normal(size=x.shape)
+    h = 1e-7
+    fp, fm = P.forces(sys_, x + h * du, 0.0), P.forces(sys_, x - h * du, 0.0)
+    np.testing.assert_allclose(-(fp - fm).ravel() / (2 * h), K @ du.ravel(), rtol=1e-5, atol=1e-5)
