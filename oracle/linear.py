@@ -74,7 +74,10 @@ def natural_frequencies(x, ends, k, l0, mass, pinned, count: int = 2, ground=Non
     dof = free_dofs(pinned)
     Kf = K[dof][:, dof].tocsc()
     Mf = sp.diags(np.repeat(mass, 3)[dof]).tocsc()
-    w2, vec = spla.eigsh(Kf, k=count, M=Mf, sigma=0.0, which="LM")
+    # a fixed start vector: ARPACK's own draws from a generator that earlier calls advance,
+    # so within a degenerate eigenspace the returned vectors would depend on call history
+    v0 = np.random.default_rng(12345).uniform(-1.0, 1.0, len(dof))
+    w2, vec = spla.eigsh(Kf, k=count, M=Mf, sigma=0.0, which="LM", v0=v0)
     order = np.argsort(w2)
     modes = np.zeros((count, 3 * len(x)))
     modes[:, dof] = vec[:, order].T

@@ -93,12 +93,24 @@ struct ApplyArgs {
     float ground_z, ground_k;
 };
 
+// 1/sqrt(s) to FP64 accuracy: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - s y^2) / 2 (each roughly doubles the correct bits), far cheaper than a
+// correctly rounded square root followed by a division.
+__device__ __forceinline__ double rsqrt_fp64(double s) {
+    double y = __builtin_amdgcn_rsq(s);
+    for (int it = 0; it < 2; ++it) {
+        const double e = __builtin_fma(-(s * y), y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // Contribution of spring (i, j) to (K u)_i: k [n n^T + (1 - l0/l)(I - n n^T)] (u_i - u_j).
 __device__ __forceinline__ void spring_hessian(float4 xi, float4 xj, double u0, double u1, double u2, double v0,
                                                double v1, double v2, double kk, double l0, double& k0, double& k1,
                                                double& k2) {
     const double dx = (double)xj.x - (double)xi.x, dy = (double)xj.y - (double)xi.y, dz = (double)xj.z - (double)xi.z;
-    const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    const double il = rsqrt_fp64(dx * dx + dy * dy + dz * dz);
     const double nx = dx * il, ny = dy * il, nz = dz * il;
     const double d0 = u0 - v0, d1 = u1 - v1, d2 = u2 - v2;
     const double nd = nx * d0 + ny * d1 + nz * d2;
