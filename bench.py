@@ -399,7 +399,7 @@ def main(argv=None):
     ap.add_argument("--held-pools", type=int, default=1, help="surrogate: held-out pools")
     ap.add_argument("--draws", type=int, default=8, help="surrogate: actuation draws simulated per robot")
     ap.add_argument("--epochs", type=int, default=150, help="surrogate: training epochs")
-    ap.add_argument("--width", type=int, default=512, help="surrogate: hidden layer width")
+    ap.add_argument("--width", type=int, default=768, help="surrogate: hidden layer width")
     ap.add_argument("--lr", type=float, default=2e-3, help="surrogate: initial learning rate")
     ap.add_argument("--lr-final", type=float, default=0.0, help="surrogate: final learning rate of the cosine schedule (-1: constant)")
     ap.add_argument("--dump", default="", help="surrogate: directory to save the data set to (npz)")

@@ -82,7 +82,7 @@ class Standardiser:
 
 class Surrogate:
     def __init__(self, X: np.ndarray, D: np.ndarray, epochs: int = 150, batch: int = 1024, lr: float = 2e-3,
-                 seed: int = 4, max_rows: int = 4096, width: int = 512, lr_final: float = 0.0):
+                 seed: int = 4, max_rows: int = 4096, width: int = 768, lr_final: float = 0.0):
         """width: hidden layer width (three hidden layers); lr_final: end of the cosine
         learning-rate schedule (None: constant lr)."""
         self.xs, self.ds = Standardiser.fit(X), Standardiser.fit(D)
