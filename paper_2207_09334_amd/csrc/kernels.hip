@@ -1030,7 +1030,11 @@ adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, 
     xbl[3 * i + 2] = xb1[3 * i + 2] + wz_contact + zb;
 }
 
-template <bool ACT>
+// LPM lanes per mass (1, 2 or 4; the simulation's lanes per mass): with more than one, lane j
+// of a mass takes its incidence rows j, j + LPM, ... and the partial sums are combined by the
+// same fixed cross-lane pairing as the step's; each incidence's sensitivity is still
+// accumulated by exactly one lane.
+template <bool ACT, int LPM>
 __global__ void __launch_bounds__(1024)
 adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, const float* __restrict__ xbl,
                   float* __restrict__ xb0, const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
@@ -1045,20 +1049,36 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     const int b = logical_block(nblk);
     if (b >= nblk) return;
     const int base = b * block;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = (int)blockDim.x;
+    const int m = t / LPM, sub = t % LPM;
     const float* fac = factor;
     if (ACT && stage_factors) {   // small tables: one LDS copy per workgroup, no dependent global load
-        for (int q = t; q <= n_factor; q += block) sfac[q] = factor[q];
-        fac = sfac;   // visible after the barrier in stage_positions
+        for (int q = t; q <= n_factor; q += nt) sfac[q] = factor[q];
+        fac = sfac;   // visible after the barrier below
     }
-    {
+    int own;
+    if constexpr (LPM == 1) {
         float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
         if (base + t < n) wt = w[base + t];
         sw[t] = wt;
         const int h0 = halo_ptr[b], h1 = halo_ptr[b + 1];
         for (int h = h0 + t; h < h1; h += block) sw[block + (h - h0)] = w[halo_idx[h]];
+        own = stage_positions(sx, x, halo_ptr, halo_idx, lane_mass, b, base, n, block);
+    } else {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = t; q < block; q += nt) {
+            sx[q] = base + q < n ? x[base + q] : z;
+            sw[q] = base + q < n ? w[base + q] : z;
+        }
+        const int h0 = halo_ptr[b], h1 = halo_ptr[b + 1];
+        for (int h = h0 + t; h < h1; h += nt) {
+            const int j = halo_idx[h];
+            sx[block + (h - h0)] = x[j];
+            sw[block + (h - h0)] = w[j];
+        }
+        __syncthreads();
+        own = lane_mass[base + m];
     }
-    const int own = stage_positions(sx, x, halo_ptr, halo_idx, lane_mass, b, base, n, block);
     const float4 xi = sx[own];
     const float4 wi = sw[own];
     float ax = 0.f, ay = 0.f, az = 0.f;
@@ -1089,21 +1109,23 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
             }
         }
     };
-    const int s = __builtin_amdgcn_readfirstlane((base + t) >> 6);
+    const int s = __builtin_amdgcn_readfirstlane((base + (LPM == 1 ? t : m)) >> 6);
     if (s < nslice) {
-        const int lane = t & 63;
+        const int lane = (LPM == 1 ? t : m) & 63;
         const int e0 = __builtin_amdgcn_readfirstlane(slice_ptr[s]);
         const int wdt = __builtin_amdgcn_readfirstlane((slice_ptr[s + 1] - e0) >> 6);
-        constexpr int B = 8;   // entries whose loads are in flight together
-        int r = 0;
-        for (; r + B <= wdt; r += B) {
+        constexpr int B = LPM == 1 ? 8 : 4;   // rows whose loads are in flight together
+        // this lane's rows: sub, sub + LPM, ... (all rows when LPM == 1)
+        const int rows = (wdt - sub + LPM - 1) / LPM;
+        int k = 0;
+        for (; k + B <= rows; k += B) {
             int slot[B], g[B];
             float2 c[B];
             float f[B];
             double2 acc[B];
 #pragma unroll
             for (int u = 0; u < B; ++u) {
-                const int e = e0 + (r + u) * 64 + lane;
+                const int e = e0 + ((k + u) * LPM + sub) * 64 + lane;
                 slot[u] = nbr[e];
                 c[u] = kl[e];
                 g[u] = ACT ? (int)grp[e] : n_factor;
@@ -1112,16 +1134,22 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
 #pragma unroll
             for (int u = 0; u < B; ++u) f[u] = ACT ? fac[g[u]] : 1.0f;
 #pragma unroll
-            for (int u = 0; u < B; ++u) one(e0 + (r + u) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
+            for (int u = 0; u < B; ++u) one(e0 + ((k + u) * LPM + sub) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
         }
-        for (; r < wdt; ++r) {
-            const int e = e0 + r * 64 + lane;
+        for (; k < rows; ++k) {
+            const int e = e0 + (k * LPM + sub) * 64 + lane;
             const int g = ACT ? (int)grp[e] : n_factor;
             one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
         }
     }
+#pragma unroll
+    for (int o = 1; o < LPM; o <<= 1) {
+        ax += __shfl_xor(ax, o, 64);
+        ay += __shfl_xor(ay, o, 64);
+        az += __shfl_xor(az, o, 64);
+    }
     const int i = base + own;
-    if (i >= n) return;
+    if (sub != 0 || i >= n) return;
     xb0[3 * i + 0] = xbl[3 * i + 0] + ax;
     xb0[3 * i + 1] = xbl[3 * i + 1] + ay;
     xb0[3 * i + 2] = xbl[3 * i + 2] + az;
@@ -1311,14 +1339,22 @@ hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float
     // the factor table goes to LDS when small (kAdjStagedFactors entries at most)
     const int stage = d.grp && d.n_factor + 1 <= kAdjStagedFactors ? 1 : 0;
     const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (stage ? (size_t)(d.n_factor + 1) * sizeof(float) : 0);
-    if (d.grp)
-        hipLaunchKernelGGL(adj_gather_kernel<true>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
-                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots, stage);
-    else
-        hipLaunchKernelGGL(adj_gather_kernel<false>, dim3(grid_for(d.nblk)), dim3(d.block), lds, st, x, w, xbl, xb0,
-                           d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx, d.lane_mass, factor, sens,
-                           d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.lds_slots, stage);
+    const int lanes = d.lanes == 2 || d.lanes == 4 ? d.lanes : 1;
+    const dim3 g(grid_for(d.nblk)), th((unsigned)(d.block * lanes));
+    auto go = [&](auto k) {
+        hipLaunchKernelGGL(k, g, th, lds, st, x, w, xbl, xb0, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
+                           d.lane_mass, factor, sens, d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice,
+                           d.block, d.lds_slots, stage);
+    };
+    if (d.grp) {
+        if (lanes == 4) go(adj_gather_kernel<true, 4>);
+        else if (lanes == 2) go(adj_gather_kernel<true, 2>);
+        else go(adj_gather_kernel<true, 1>);
+    } else {
+        if (lanes == 4) go(adj_gather_kernel<false, 4>);
+        else if (lanes == 2) go(adj_gather_kernel<false, 2>);
+        else go(adj_gather_kernel<false, 1>);
+    }
     return hipGetLastError();
 }
 

@@ -36,9 +36,9 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
-def _compare(w, T, K, loss_w, fd_h=None):
+def _compare(w, T, K, loss_w, fd_h=None, **create):
     lat, sys_, x0 = oracle_problem(w)
-    sim, _, _ = PR.create(w, x0=x0)
+    sim, _, _ = PR.create(w, x0=x0, **create)
     loss_g = CR.cronos_rollout(sim, T, K, loss_w)
     dp, da, dx, dv = CR.cronos_rollout_backward(sim, want_state=True)
     loss_o, op, oa, ox, ov = A.rollout_grad(sys_, x0, np.zeros_like(x0), 0, T, loss_w)
@@ -80,6 +80,25 @@ def test_adjoint_contact_friction_vs_oracle_and_fd():
     loss_w = np.zeros_like(lat.x)
     loss_w[:, 0] = lat.mass / lat.mass.sum()
     _compare(w, 200, 100, loss_w, fd_h=1e-7)
+
+
+def test_adjoint_four_lanes_per_mass_vs_oracle_and_fd():
+    """The same bar with 4 lanes per mass in 64-mass workgroups (the autotuner's pick for the
+    quadruped) in both the forward steps and the adjoint gather: the actuated cube on the plane
+    against the oracle's adjoint and central differences, and the quadruped against the
+    oracle's adjoint."""
+    w = _actuated_cube(ground=True)
+    say("case: adjoint with 4 lanes per mass: actuated cube 200 steps, quadruped 300 steps")
+    lat = L.build(w)
+    loss_w = np.zeros_like(lat.x)
+    loss_w[:, 0] = lat.mass / lat.mass.sum()
+    sim, _, _ = _compare(w, 200, 100, loss_w, fd_h=1e-7, lanes_per_mass=4, block_masses=64)
+    assert CR.cronos_launch_config(sim)["lanes_per_mass"] == 4
+    w = W.quadruped()
+    lat = L.build(w)
+    loss_w = np.zeros_like(lat.x)
+    loss_w[:, 0] = lat.mass / lat.mass.sum()
+    _compare(w, 300, 100, loss_w, lanes_per_mass=4, block_masses=64)
 
 
 def test_adjoint_quadruped_vs_oracle():
