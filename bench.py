@@ -80,13 +80,28 @@ def cpu_baseline(workload, steps: int):
     lat = L.build(workload)
     sys_ = P.system_from(lat, workload)
     x, v = lat.x.copy(), np.zeros_like(lat.x)
-    x, v = P.step(sys_, x, v, 0)          # untimed first step (page-in)
-    t0 = time.perf_counter()
-    x, v = P.run(sys_, x, v, 1, steps)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):     # one thread, also for any BLAS call NumPy makes
+        x, v = P.step(sys_, x, v, 0)      # untimed first step (page-in)
+        t0 = time.perf_counter()
+        x, v = P.run(sys_, x, v, 1, steps)
+        dt = time.perf_counter() - t0
     return {"value": lat.n_springs * steps / dt, "unit": "spring-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} FP64 NumPy steps of the full {workload.name} lattice "
-                      f"({lat.n_masses} masses, {lat.n_springs} springs), single thread, {dt:.1f} s"}
+                      f"({lat.n_masses} masses, {lat.n_springs} springs), single thread on {cpu_model()} "
+                      f"({len(os.sched_getaffinity(0))} cores available), {dt:.1f} s"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def adjoint_bench(args) -> dict:
