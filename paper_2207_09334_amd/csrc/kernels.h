@@ -51,6 +51,7 @@ struct DeviceArrays {
     int32_t* sp_ptr = nullptr;           //   per-workgroup record ranges
     int32_t max_sp = 0;                  //   and the largest record count of a workgroup
     int32_t resident = 0;                // one workgroup holds the system (see launch_resident)
+    int32_t resident_staged = 0;         // entries the resident form copies into LDS (0: read from memory)
     uint16_t* grp = nullptr;             // per entry index into factor[], or null
     int32_t* halo_ptr = nullptr;
     int32_t* halo_idx = nullptr;
@@ -91,6 +92,9 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
 // Whether launch_step computes the actuation factors inside the step (actuated systems in a
 // compact table form); otherwise an actuation launch must precede each step.
 bool fused_actuation(const DeviceArrays& d);
+// Dynamic LDS bytes of one step workgroup (positions, table, factors; the resident form adds its
+// staged entries).
+size_t step_lds_bytes(const DeviceArrays& d);
 // `steps` steps of a system held by one workgroup (resident form; table form, block >= n):
 // positions stay in LDS between steps; the first step kicks for dtv0.  Reads x[cur], v[cur],
 // writes x[cur ^ 1], v[cur ^ 1]; advances the device step counter by `steps`.

@@ -437,6 +437,7 @@ struct ResidentArgs {
     long long* step_out;        // receives the index after the launch (the other slot)
     int steps;
     float dtv0;
+    int staged;                 // compact entries copied into LDS after the factors (0: none)
 };
 
 // Step modes: explicit (k, L0) per entry, compact entries with the parameter table, split.
@@ -728,7 +729,9 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
 // registers; each step computes its actuation factors in place (the same formula as
 // actuation_kernel), gathers, integrates, and after a barrier overwrites the positions.  The
 // device step counter advances by K.  The first step kicks for dtv0 (Verlet's dt / 2).
-template <bool ACT, bool EXACT, int BATCH>
+// STAGED: the compact entries are copied into LDS once (r.staged of them, after the factors),
+// so no step waits on a memory load.
+template <bool ACT, bool EXACT, int BATCH, bool STAGED>
 __global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, ResidentArgs r) {
     extern __shared__ float4 sx[];
     const uint32_t tbase = table_base(a.lds_slots);
@@ -736,6 +739,12 @@ __global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, 
     float* sf = reinterpret_cast<float*>(st + a.n_table);
     const int t = (int)threadIdx.x;
     for (int q = t; q < a.n_table; q += a.block) st[q] = a.table[q];
+    const uint32_t* pk = a.packed;
+    if (STAGED) {
+        uint32_t* se = reinterpret_cast<uint32_t*>(sf + a.max_local_groups + 1);
+        for (int q = t; q < r.staged; q += a.block) se[q] = a.packed[q];
+        pk = se;
+    }
     sx[t] = t < a.n ? a.xin[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int own = a.lane_mass[t];
     const bool live = own < a.n;
@@ -760,9 +769,9 @@ __global__ void __launch_bounds__(1024) step_resident(StepArgs a, StepParams p, 
         const float4 xi = sx[own];
         float fx, fy, fz;
         const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
-        if (mode == kPlain) gather_table<ACT, kPlain, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
-        else if (mode == kExactZ) gather_table<ACT, kExactZ, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
-        else gather_table<ACT, kExactAll, kExactBatch<BATCH>>(tbase, sf, xi, s, a.nslice, a.slice_ptr, a.packed, fx, fy, fz);
+        if (mode == kPlain) gather_table<ACT, kPlain, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, pk, fx, fy, fz);
+        else if (mode == kExactZ) gather_table<ACT, kExactZ, BATCH>(tbase, sf, xi, s, a.nslice, a.slice_ptr, pk, fx, fy, fz);
+        else gather_table<ACT, kExactAll, kExactBatch<BATCH>>(tbase, sf, xi, s, a.nslice, a.slice_ptr, pk, fx, fy, fz);
         integrate(p, k == 0 ? r.dtv0 : p.dtv, xi, fx, fy, fz, fext, vx, vy, vz, xo, nullptr);
         __syncthreads();  // every lane has read step k's positions
         if (live) sx[own] = xo;
@@ -1174,7 +1183,8 @@ hipError_t step_static_lds(size_t* bytes) {
                         (const void*)step_persistent<true, false, 8, kSplit>,
                         (const void*)step_kernel<false, true, 4, kNarrow>,
                         (const void*)step_lanes_kernel<true, true, 4, false>,
-                        (const void*)step_lanes_kernel<false, true, 2, true>};
+                        (const void*)step_lanes_kernel<false, true, 2, true>,
+                        (const void*)step_resident<false, true, 4, true>, (const void*)step_resident<true, true, 4, false>};
     *bytes = 0;
     for (const void* k : ks) {
         hipFuncAttributes at{};
@@ -1256,12 +1266,18 @@ hipError_t launch_resident(const DeviceArrays& d, int cur, const StepParams& p, 
                d.lane_mass, d.factor, d.fext, nullptr, d.packed, d.narrow, d.table, d.blk_groups, d.sp_rec, d.sp_grp,
                d.sp_ptr, (int)d.n, (int)d.nblk, (int)d.nslice, d.block, d.n_table, d.lds_slots, d.max_local_groups,
                d.narrow_tb, 0, d.phase, d.amp, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), cycles};
-    ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), steps, dtv0};
-    const size_t lds = step_lds_bytes(d);
+    ResidentArgs r{d.phase, d.amp, cycles, d.step_ctr + (cur & 1), d.step_ctr + ((cur & 1) ^ 1), steps, dtv0,
+                   d.resident_staged};
+    const size_t lds = step_lds_bytes(d) + (size_t)d.resident_staged * sizeof(uint32_t);
     const bool act = d.grp != nullptr, ex = p.exact != 0;
     auto go = [&](auto k) { hipLaunchKernelGGL(k, dim3(1), dim3(d.block), lds, st, a, p, r); };
-    if (act) ex ? go(step_resident<true, true, 4>) : go(step_resident<true, false, 4>);
-    else ex ? go(step_resident<false, true, 4>) : go(step_resident<false, false, 4>);
+    if (d.resident_staged) {
+        if (act) ex ? go(step_resident<true, true, 4, true>) : go(step_resident<true, false, 4, true>);
+        else ex ? go(step_resident<false, true, 4, true>) : go(step_resident<false, false, 4, true>);
+    } else {
+        if (act) ex ? go(step_resident<true, true, 4, false>) : go(step_resident<true, false, 4, false>);
+        else ex ? go(step_resident<false, true, 4, false>) : go(step_resident<false, false, 4, false>);
+    }
     return hipGetLastError();
 }
 

@@ -796,6 +796,15 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             D.resident = (d->flags & CRONOS_RESIDENT) && L.nblk == 1 && hsp_rec.empty() ? 1 : 0;
             if (sim->actuated) TRY(upload(&D.blk_groups, hblk_groups.data(), hblk_groups.size()));
             D.max_local_groups = max_local_groups;
+            if (D.resident && D.packed) {
+                // the resident form keeps the entries in LDS as well when they fit beside the
+                // positions, the (k, L0) table and the factors
+                int dev = 0, cap = 0;
+                HIP_TRY(hipGetDevice(&dev));
+                HIP_TRY(hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+                if (cronos::step_lds_bytes(D) + (size_t)entries * sizeof(uint32_t) <= (size_t)cap)
+                    D.resident_staged = (int32_t)entries;
+            }
         }
         if (sim->actuated) TRY(upload(&D.grp, hg.data(), entries));
         TRY(upload(&D.halo_ptr, L.halo_ptr.data(), L.halo_ptr.size()));
