@@ -111,8 +111,22 @@ hipError_t launch_actuation(const DeviceArrays& d, unsigned long long cycles, in
 // Adjoint of one step (see kernels.hip).
 hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float* vstar, const float* xb1,
                             const float* vb1, float4* w, float* vb0, float* xbl, const StepParams& p, hipStream_t st);
+// adj_local of the previous step fused into the gather's end (x == nullptr: none); the
+// buffers w and xbl are the previous step's, distinct from the ones the gather reads.
+struct AdjNext {
+    const float4* x = nullptr;      // positions at the previous step's start
+    const float* vstar = nullptr;   // its v* (before friction)
+    const float* vb1 = nullptr;     // v_bar after the previous step (written by this step's adj_local)
+    float4* w = nullptr;
+    float* vb0 = nullptr;
+    float* xbl = nullptr;
+};
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor = nullptr);
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             const StepParams& p, const AdjNext& next);
+// Actuation factors of steps n0 .. n0 + steps - 1 in one launch, row k at out + k * stride.
+hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycles, long long n0, int steps,
+                                  float* out, long long stride, hipStream_t st);
 hipError_t launch_forces(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 
 // Lanczos iterations for the natural frequencies (modes.hip), FP64.

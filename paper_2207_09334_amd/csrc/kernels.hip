@@ -845,6 +845,19 @@ actuation_kernel(const float* __restrict__ phase, const float* __restrict__ amp,
     if (advance && blockIdx.x == 0 && threadIdx.x == 0) *step_out = n + 1;
 }
 
+// The factors of steps n0, n0 + 1, ..., n0 + gridDim.y - 1 (one per blockIdx.y), row k at
+// out + k * stride: the same formula as actuation_kernel, for a recomputed segment at once.
+__global__ void __launch_bounds__(256)
+actuation_steps_kernel(const float* __restrict__ phase, const float* __restrict__ amp, unsigned long long cycles,
+                       long long n0, float* __restrict__ out, int n_factor, long long stride) {
+    const int k = (int)blockIdx.y;
+    const float u = period_fraction(n0 + k, cycles);
+    const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    float* f = out + (size_t)k * (size_t)stride;
+    if (g < n_factor) f[g] = actuation_factor(amp[g], phase[g], u);
+    else if (g == n_factor) f[g] = 1.0f;
+}
+
 // ---------------------------------------------------------------- FP64 diagnostics
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -988,26 +1001,25 @@ __global__ void diag_body_kernel(const double* __restrict__ part, const int32_t*
 // spring sum; adj_gather adds the spring sum with the same LDS-staged incidence walk as the
 // step, and accumulates each actuated spring's sensitivity in FP64, half from each end.
 
-__global__ void __launch_bounds__(256)
-adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, const float* __restrict__ xb1,
-                 const float* __restrict__ vb1, float4* __restrict__ w, float* __restrict__ vb0,
-                 float* __restrict__ xbl, int n, StepParams p) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// adj_local for mass i, given its x_bar' (bx, by, bz) and v_bar' (vb1).
+__device__ __forceinline__ void adj_local_one(int i, const float4* __restrict__ x, const float* __restrict__ vstar,
+                                              float bx, float by, float bz, const float* __restrict__ vb1,
+                                              float4* __restrict__ w, float* __restrict__ vb0,
+                                              float* __restrict__ xbl, const StepParams& p) {
     const float4 xi = x[i];
     const float inv_m = xi.w;
-    const float tx = __builtin_fmaf(p.dt, xb1[3 * i + 0], vb1[3 * i + 0]);
-    const float ty = __builtin_fmaf(p.dt, xb1[3 * i + 1], vb1[3 * i + 1]);
-    const float tz = __builtin_fmaf(p.dt, xb1[3 * i + 2], vb1[3 * i + 2]);
+    const float tx = __builtin_fmaf(p.dt, bx, vb1[3 * i + 0]);
+    const float ty = __builtin_fmaf(p.dt, by, vb1[3 * i + 1]);
+    const float tz = __builtin_fmaf(p.dt, bz, vb1[3 * i + 2]);
     float gx = p.damp * tx, gy = p.damp * ty, gz = p.damp * tz;
     float zb = 0.0f;
     float wz_contact = 0.0f;
     if (inv_m == 0.0f) {
         w[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         vb0[3 * i + 0] = vb0[3 * i + 1] = vb0[3 * i + 2] = 0.0f;
-        xbl[3 * i + 0] = xb1[3 * i + 0];
-        xbl[3 * i + 1] = xb1[3 * i + 1];
-        xbl[3 * i + 2] = xb1[3 * i + 2];
+        xbl[3 * i + 0] = bx;
+        xbl[3 * i + 1] = by;
+        xbl[3 * i + 2] = bz;
         return;
     }
     const float pen = p.ground ? p.ground_z - xi.z : 0.0f;
@@ -1034,15 +1046,26 @@ adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, 
     vb0[3 * i + 0] = gx;
     vb0[3 * i + 1] = gy;
     vb0[3 * i + 2] = gz;
-    xbl[3 * i + 0] = xb1[3 * i + 0];
-    xbl[3 * i + 1] = xb1[3 * i + 1];
-    xbl[3 * i + 2] = xb1[3 * i + 2] + wz_contact + zb;
+    xbl[3 * i + 0] = bx;
+    xbl[3 * i + 1] = by;
+    xbl[3 * i + 2] = bz + wz_contact + zb;
+}
+
+__global__ void __launch_bounds__(256)
+adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, const float* __restrict__ xb1,
+                 const float* __restrict__ vb1, float4* __restrict__ w, float* __restrict__ vb0,
+                 float* __restrict__ xbl, int n, StepParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    adj_local_one(i, x, vstar, xb1[3 * i + 0], xb1[3 * i + 1], xb1[3 * i + 2], vb1, w, vb0, xbl, p);
 }
 
 // LPM lanes per mass (1, 2 or 4; the simulation's lanes per mass): with more than one, lane j
 // of a mass takes its incidence rows j, j + LPM, ... and the partial sums are combined by the
 // same fixed cross-lane pairing as the step's; each incidence's sensitivity is still
-// accumulated by exactly one lane.
+// accumulated by exactly one lane.  With nx.x set, the mass's x_bar then feeds adj_local of
+// the step before (every input of which is the mass's own), so one launch per reversed step
+// remains; nx.w and nx.xbl must not be the w and xbl this launch reads.
 template <bool ACT, int LPM>
 __global__ void __launch_bounds__(1024)
 adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, const float* __restrict__ xbl,
@@ -1051,7 +1074,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
                   const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
                   const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
                   double2* __restrict__ sens, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
-                  int block, int lds_slots, int stage_factors) {
+                  int block, int lds_slots, int stage_factors, StepParams p, AdjNext nx) {
     extern __shared__ float4 sx[];
     float4* sw = sx + lds_slots;
     float* sfac = reinterpret_cast<float*>(sw + lds_slots);   // the factor table, when staged
@@ -1159,9 +1182,11 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     }
     const int i = base + own;
     if (sub != 0 || i >= n) return;
-    xb0[3 * i + 0] = xbl[3 * i + 0] + ax;
-    xb0[3 * i + 1] = xbl[3 * i + 1] + ay;
-    xb0[3 * i + 2] = xbl[3 * i + 2] + az;
+    const float bx = xbl[3 * i + 0] + ax, by = xbl[3 * i + 1] + ay, bz = xbl[3 * i + 2] + az;
+    xb0[3 * i + 0] = bx;
+    xb0[3 * i + 1] = by;
+    xb0[3 * i + 2] = bz;
+    if (nx.x) adj_local_one(i, nx.x, nx.vstar, bx, by, bz, nx.vb1, nx.w, nx.vb0, nx.xbl, p);
 }
 
 inline int grid_for(int64_t nblk) { return (int)(((nblk + 7) / 8) * 8); }
@@ -1349,8 +1374,20 @@ hipError_t launch_adj_local(const DeviceArrays& d, const float4* x, const float*
     return hipGetLastError();
 }
 
+hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycles, long long n0, int steps,
+                                  float* out, long long stride, hipStream_t st) {
+    const unsigned grid = (unsigned)((d.n_factor + 1 + 255) / 256);
+    for (int k0 = 0; k0 < steps; k0 += 65535) {   // at most 65535 rows per launch (grid y)
+        const int rows = std::min(steps - k0, 65535);
+        hipLaunchKernelGGL(actuation_steps_kernel, dim3(grid, (unsigned)rows), dim3(256), 0, st, d.phase, d.amp, cycles,
+                           n0 + k0, out + (size_t)k0 * (size_t)stride, d.n_factor, stride);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor) {
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             const StepParams& p, const AdjNext& next) {
     if (!factor) factor = d.factor;
     // the factor table goes to LDS when small (kAdjStagedFactors entries at most)
     const int stage = d.grp && d.n_factor + 1 <= kAdjStagedFactors ? 1 : 0;
@@ -1360,7 +1397,7 @@ hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float
     auto go = [&](auto k) {
         hipLaunchKernelGGL(k, g, th, lds, st, x, w, xbl, xb0, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
                            d.lane_mass, factor, sens, d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice,
-                           d.block, d.lds_slots, stage);
+                           d.block, d.lds_slots, stage, p, next);
     };
     if (d.grp) {
         if (lanes == 4) go(adj_gather_kernel<true, 4>);

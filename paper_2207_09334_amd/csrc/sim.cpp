@@ -69,10 +69,10 @@ struct RolloutBuffers {
     float* seg_vs = nullptr;  // [K][3N]
     float* seg_f = nullptr;   // [K][n_factor + 1] actuation factors of the segment's steps
     float* lossw = nullptr;   // [3N]
-    float4* w = nullptr;      // [N]
+    float4* w[2] = {nullptr, nullptr};    // [N] adjoint force terms, alternating by reversed step
     float* xb[2] = {nullptr, nullptr};
     float* vb[2] = {nullptr, nullptr};
-    float* xbl = nullptr;
+    float* xbl[2] = {nullptr, nullptr};   // [3N] x_bar before the spring sum, alternating as w
     double2* sens = nullptr;  // [entries]
     size_t cap_seg = 0, cap_ck = 0;
     // the reverse sweep captured as one HIP graph, reused while everything it bakes in (the
@@ -122,8 +122,8 @@ void free_device(cronos_sim_t* s) {
         if (g) (void)hipGraphExecDestroy(g);
     RolloutBuffers& r = s->ro;
     if (r.bwd_graph) (void)hipGraphExecDestroy(r.bwd_graph);
-    void* rp[] = {r.seg_f, r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w, r.xb[0], r.xb[1], r.vb[0], r.vb[1], r.xbl,
-                  r.sens};
+    void* rp[] = {r.seg_f, r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w[0], r.w[1], r.xb[0], r.xb[1], r.vb[0], r.vb[1],
+                  r.xbl[0], r.xbl[1], r.sens};
     for (void* p : rp)
         if (p) (void)hipFree(p);
     if (s->h_x) (void)hipHostFree(s->h_x);
@@ -1245,12 +1245,12 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     TRY(ensure(&R.seg_vs, R.cap_seg * 3 * n));
     TRY(ensure(&R.seg_f, R.cap_seg * (size_t)(sim->d.n_factor + 1)));
     TRY(ensure(&R.lossw, 3 * n));
-    TRY(ensure(&R.w, n));
     for (int q = 0; q < 2; ++q) {
+        TRY(ensure(&R.w[q], n));
         TRY(ensure(&R.xb[q], 3 * n));
         TRY(ensure(&R.vb[q], 3 * n));
+        TRY(ensure(&R.xbl[q], 3 * n));
     }
-    TRY(ensure(&R.xbl, 3 * n));
     TRY(ensure(&R.sens, (size_t)sim->lay.slice_ptr.back()));
     // loss weights in the device order (FP32)
     std::vector<float> hw(3 * n);
@@ -1289,28 +1289,42 @@ cronos_status enqueue_reverse_sweep(cronos_sim_t* sim) {
     const int64_t n = sim->d.n;
     const cronos::DeviceArrays& D = sim->d;
     hipStream_t st = sim->stream;
-    int cur = 0;
+    int cur = 0, wc = 0;
     for (int32_t c = R.nseg - 1; c >= 0; --c) {
         const int64_t nc = R.n0 + (int64_t)c * R.K;
         const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
         HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
         const size_t fs = (size_t)D.n_factor + 1;
+        // the segment's actuation factors in one launch, then its steps
+        if (sim->actuated) HIP_TRY(cronos::launch_actuation_steps(D, sim->cycles, nc, steps, R.seg_f, (long long)fs, st));
         for (int32_t k = 0; k < steps; ++k) {
             float* fk = sim->actuated ? R.seg_f + (size_t)k * fs : nullptr;
-            if (sim->actuated) HIP_TRY(cronos::launch_actuation(D, sim->cycles, 0, st, nc + k, fk));
             HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
                                            R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
                                            R.seg_vs + (size_t)k * 3 * n, sim->p, st, fk));
         }
-        for (int32_t k = steps - 1; k >= 0; --k) {
+        // the segment's last step: adj_local on its own; every later adj_local (of step k - 1)
+        // runs at the end of the gather of step k, while the segment's states are at hand
+        const int32_t last = steps - 1;
+        HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)last * n, R.seg_vs + (size_t)last * 3 * n, R.xb[cur],
+                                         R.vb[cur], R.w[wc], R.vb[cur ^ 1], R.xbl[wc], sim->p, st));
+        for (int32_t k = last; k >= 0; --k) {
             const double t = (double)(nc + k) * sim->dt;
-            HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)k * n, R.seg_vs + (size_t)k * 3 * n, R.xb[cur],
-                                             R.vb[cur], R.w, R.vb[cur ^ 1], R.xbl, sim->p, st));
-            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w, R.xbl, R.xb[cur ^ 1], R.sens,
+            cronos::AdjNext nx;
+            if (k > 0) {
+                nx.x = R.seg_x + (size_t)(k - 1) * n;
+                nx.vstar = R.seg_vs + (size_t)(k - 1) * 3 * n;
+                nx.vb1 = R.vb[cur ^ 1];
+                nx.w = R.w[wc ^ 1];
+                nx.vb0 = R.vb[cur];
+                nx.xbl = R.xbl[wc ^ 1];
+            }
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], R.sens,
                                               std::cos(sim->omega * t), std::sin(sim->omega * t), st,
-                                              sim->actuated ? R.seg_f + (size_t)k * fs : nullptr));
+                                              sim->actuated ? R.seg_f + (size_t)k * fs : nullptr, sim->p, nx));
             cur ^= 1;
+            if (k > 0) wc ^= 1;
         }
     }
     return CRONOS_OK;
