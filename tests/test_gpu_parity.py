@@ -414,6 +414,41 @@ def test_resident_form_matches_oracle_cube_1000():
     assert worst <= X_TOL
 
 
+def test_resident_form_entries_beyond_lds_bitwise_equal():
+    """A dense 1000-point best-candidate body (springs to 2.2 mean spacings, degree up to 43;
+    rest lengths rounded to 16 levels so that the (k, L0) table holds them): its padded
+    compact entries (about 42k, 169 KB) do not fit in LDS beside the positions, so the resident
+    form reads them from memory each step; still bitwise the per-step launches' states."""
+    import dataclasses
+    from oracle import candidate as OC
+    pw = W.candidate_bar(1000, size=(0.1, 0.02, 0.02), seed=9)
+    pw = dataclasses.replace(pw, cutoff=2.2 * pw.length_ref)
+    pts = OC.best_candidate_points(pw.size, pw.n_points, pw.n_candidates, pw.k_nn, pw.seed)
+    ends = OC.cutoff_springs(pts, pw.cutoff)
+    d = pts[ends[:, 1]] - pts[ends[:, 0]]
+    length = np.sqrt((d * d).sum(axis=1))
+    lo, hi = length.min(), length.max()
+    rest = lo + np.round((length - lo) / (hi - lo) * 15.0) * (hi - lo) / 15.0
+    degree = np.bincount(ends.ravel(), minlength=len(pts))
+    say(f"case: resident form, dense candidate body: {len(ends)} springs, degree up to {degree.max()}")
+    assert degree.max() >= 40
+    kw = dict(mass=np.full(len(pts), 0.1), ends=ends, k=np.full(len(ends), 1.0e4), rest=rest,
+              pinned=(pts[:, 0] < pw.pin_x).astype(np.uint8), gravity=(0.0, 0.0, -9.81), damping=0.001, dt=1.0e-4)
+    ref = CR.cronos_create(pts, **kw)
+    res = CR.cronos_create(pts, flags=CR.RESIDENT, **kw)
+    assert CR.cronos_launch_config(res)["step_form"] == "resident"
+    assert CR.cronos_launch_config(ref)["step_form"] in ("table", "narrow")
+    for chunk in (1, 99, 300):
+        CR.cronos_step(ref, chunk)
+        CR.cronos_step(res, chunk)
+        a, b = CR.cronos_read_state(ref), CR.cronos_read_state(res)
+        assert a[2] == b[2]
+        assert np.isfinite(a[0]).all()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    ref.close()
+    res.close()
+
+
 def test_resident_flag_ignored_for_large_systems():
     sim, _, _ = PR.create(W.cantilever(40, 8, 8), flags=CR.RESIDENT)
     assert CR.cronos_launch_config(sim)["step_form"] == "narrow"
