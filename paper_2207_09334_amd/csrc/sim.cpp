@@ -64,10 +64,14 @@ struct RolloutBuffers {
     bool valid = false;
     float4* ck_x = nullptr;   // [nseg][N]
     float* ck_v = nullptr;    // [nseg][3N]
-    float4* seg_x = nullptr;  // [K+1][N]
-    float* seg_v = nullptr;   // [K+1][3N]
-    float* seg_vs = nullptr;  // [K][3N]
-    float* seg_f = nullptr;   // [K][n_factor + 1] actuation factors of the segment's steps
+    // two segment buffers: the reverse sweep of one segment runs while the next one (earlier in
+    // time) is recomputed into the other, on a second stream
+    float4* seg_x[2] = {nullptr, nullptr};  // [K+1][N]
+    float* seg_v[2] = {nullptr, nullptr};   // [K+1][3N]
+    float* seg_vs[2] = {nullptr, nullptr};  // [K][3N]
+    float* seg_f[2] = {nullptr, nullptr};   // [K][n_factor + 1] actuation factors of the segment's steps
+    hipStream_t side = nullptr;             // the recompute's stream (default priority)
+    hipEvent_t ev[5] = {};                  // fork, recomputed[2], reversed[2]
     float* lossw = nullptr;   // [3N]
     float4* w[2] = {nullptr, nullptr};    // [N] adjoint force terms, alternating by reversed step
     float* xb[2] = {nullptr, nullptr};
@@ -122,7 +126,11 @@ void free_device(cronos_sim_t* s) {
         if (g) (void)hipGraphExecDestroy(g);
     RolloutBuffers& r = s->ro;
     if (r.bwd_graph) (void)hipGraphExecDestroy(r.bwd_graph);
-    void* rp[] = {r.seg_f, r.ck_x, r.ck_v, r.seg_x, r.seg_v, r.seg_vs, r.lossw, r.w[0], r.w[1], r.xb[0], r.xb[1], r.vb[0], r.vb[1],
+    for (hipEvent_t e : r.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r.side) (void)hipStreamDestroy(r.side);
+    void* rp[] = {r.seg_f[0], r.seg_f[1], r.ck_x, r.ck_v, r.seg_x[0], r.seg_x[1], r.seg_v[0], r.seg_v[1], r.seg_vs[0],
+                  r.seg_vs[1], r.lossw, r.w[0], r.w[1], r.xb[0], r.xb[1], r.vb[0], r.vb[1],
                   r.xbl[0], r.xbl[1], r.sens};
     for (void* p : rp)
         if (p) (void)hipFree(p);
@@ -1234,16 +1242,28 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
     const int32_t nseg = (int32_t)((n_steps + K - 1) / K);
     if (R.cap_seg < (size_t)K || R.cap_ck < (size_t)nseg) {
         HIP_TRY(hipStreamSynchronize(sim->stream));
-        release(R.ck_x); release(R.ck_v); release(R.seg_x); release(R.seg_v); release(R.seg_vs); release(R.seg_f);
+        release(R.ck_x);
+        release(R.ck_v);
+        for (int q = 0; q < 2; ++q) {
+            release(R.seg_x[q]);
+            release(R.seg_v[q]);
+            release(R.seg_vs[q]);
+            release(R.seg_f[q]);
+        }
         R.cap_seg = std::max<size_t>(R.cap_seg, (size_t)K);
         R.cap_ck = std::max<size_t>(R.cap_ck, (size_t)std::max(nseg, 1));
     }
     TRY(ensure(&R.ck_x, R.cap_ck * n));
     TRY(ensure(&R.ck_v, R.cap_ck * 3 * n));
-    TRY(ensure(&R.seg_x, (R.cap_seg + 1) * n));
-    TRY(ensure(&R.seg_v, (R.cap_seg + 1) * 3 * n));
-    TRY(ensure(&R.seg_vs, R.cap_seg * 3 * n));
-    TRY(ensure(&R.seg_f, R.cap_seg * (size_t)(sim->d.n_factor + 1)));
+    for (int q = 0; q < 2; ++q) {
+        TRY(ensure(&R.seg_x[q], (R.cap_seg + 1) * n));
+        TRY(ensure(&R.seg_v[q], (R.cap_seg + 1) * 3 * n));
+        TRY(ensure(&R.seg_vs[q], R.cap_seg * 3 * n));
+        TRY(ensure(&R.seg_f[q], R.cap_seg * (size_t)(sim->d.n_factor + 1)));
+    }
+    if (!R.side) HIP_TRY(hipStreamCreateWithFlags(&R.side, hipStreamNonBlocking));
+    for (hipEvent_t& e : R.ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     TRY(ensure(&R.lossw, 3 * n));
     for (int q = 0; q < 2; ++q) {
         TRY(ensure(&R.w[q], n));
@@ -1282,50 +1302,76 @@ namespace {
 
 // Enqueues the reverse sweep of the recorded rollout on the simulation's stream: for each
 // segment from the last, restore its checkpoint, recompute its states forward (keeping v* and
-// each step's actuation factors), then run the adjoint of each of its steps backwards.  No
-// host synchronisation and no memsets, so it can be captured in a HIP graph.
+// each step's actuation factors), then run the adjoint of each of its steps backwards.  The
+// recompute runs one segment ahead on a second stream, into the other segment buffer, so it
+// overlaps the adjoint kernels (both are small launches on bodies of this size); events
+// order the two.  No host synchronisation and no memsets, so it can be captured in a HIP
+// graph (the second stream joins the capture through the first event).
 cronos_status enqueue_reverse_sweep(cronos_sim_t* sim) {
     RolloutBuffers& R = sim->ro;
     const int64_t n = sim->d.n;
     const cronos::DeviceArrays& D = sim->d;
     hipStream_t st = sim->stream;
-    int cur = 0, wc = 0;
-    for (int32_t c = R.nseg - 1; c >= 0; --c) {
+    const size_t fs = (size_t)D.n_factor + 1;
+    hipEvent_t fork = R.ev[0], *done_fwd = R.ev + 1, *done_rev = R.ev + 3;
+    // segment c into buffer c & 1 on the side stream: restore its checkpoint, recompute its
+    // states forward keeping v* and each step's actuation factors
+    auto recompute = [&](int32_t c) -> cronos_status {
+        const int p = c & 1;
         const int64_t nc = R.n0 + (int64_t)c * R.K;
         const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
-        HIP_TRY(hipMemcpyAsync(R.seg_x, R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(R.seg_v, R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
-        const size_t fs = (size_t)D.n_factor + 1;
-        // the segment's actuation factors in one launch, then its steps
-        if (sim->actuated) HIP_TRY(cronos::launch_actuation_steps(D, sim->cycles, nc, steps, R.seg_f, (long long)fs, st));
+        HIP_TRY(hipMemcpyAsync(R.seg_x[p], R.ck_x + (size_t)c * n, n * sizeof(float4), hipMemcpyDeviceToDevice, R.side));
+        HIP_TRY(hipMemcpyAsync(R.seg_v[p], R.ck_v + (size_t)c * 3 * n, 3 * n * sizeof(float), hipMemcpyDeviceToDevice,
+                               R.side));
+        if (sim->actuated)
+            HIP_TRY(cronos::launch_actuation_steps(D, sim->cycles, nc, steps, R.seg_f[p], (long long)fs, R.side));
         for (int32_t k = 0; k < steps; ++k) {
-            float* fk = sim->actuated ? R.seg_f + (size_t)k * fs : nullptr;
-            HIP_TRY(cronos::launch_step_io(D, R.seg_x + (size_t)k * n, R.seg_v + (size_t)k * 3 * n,
-                                           R.seg_x + (size_t)(k + 1) * n, R.seg_v + (size_t)(k + 1) * 3 * n,
-                                           R.seg_vs + (size_t)k * 3 * n, sim->p, st, fk));
+            float* fk = sim->actuated ? R.seg_f[p] + (size_t)k * fs : nullptr;
+            HIP_TRY(cronos::launch_step_io(D, R.seg_x[p] + (size_t)k * n, R.seg_v[p] + (size_t)k * 3 * n,
+                                           R.seg_x[p] + (size_t)(k + 1) * n, R.seg_v[p] + (size_t)(k + 1) * 3 * n,
+                                           R.seg_vs[p] + (size_t)k * 3 * n, sim->p, R.side, fk));
         }
+        HIP_TRY(hipEventRecord(done_fwd[p], R.side));
+        return CRONOS_OK;
+    };
+    // the side stream starts after what the main stream holds (and joins a capture this way)
+    HIP_TRY(hipEventRecord(fork, st));
+    HIP_TRY(hipStreamWaitEvent(R.side, fork, 0));
+    TRY(recompute(R.nseg - 1));
+    int cur = 0, wc = 0;
+    for (int32_t c = R.nseg - 1; c >= 0; --c) {
+        const int p = c & 1;
+        const int64_t nc = R.n0 + (int64_t)c * R.K;
+        const int32_t steps = (int32_t)std::min<int64_t>(R.K, R.T - (int64_t)c * R.K);
+        if (c > 0) {
+            // the earlier segment's buffer was last read by the reverse sweep of segment c + 1
+            if (c + 1 < R.nseg) HIP_TRY(hipStreamWaitEvent(R.side, done_rev[(c - 1) & 1], 0));
+            TRY(recompute(c - 1));
+        }
+        HIP_TRY(hipStreamWaitEvent(st, done_fwd[p], 0));
         // the segment's last step: adj_local on its own; every later adj_local (of step k - 1)
         // runs at the end of the gather of step k, while the segment's states are at hand
         const int32_t last = steps - 1;
-        HIP_TRY(cronos::launch_adj_local(D, R.seg_x + (size_t)last * n, R.seg_vs + (size_t)last * 3 * n, R.xb[cur],
-                                         R.vb[cur], R.w[wc], R.vb[cur ^ 1], R.xbl[wc], sim->p, st));
+        HIP_TRY(cronos::launch_adj_local(D, R.seg_x[p] + (size_t)last * n, R.seg_vs[p] + (size_t)last * 3 * n,
+                                         R.xb[cur], R.vb[cur], R.w[wc], R.vb[cur ^ 1], R.xbl[wc], sim->p, st));
         for (int32_t k = last; k >= 0; --k) {
             const double t = (double)(nc + k) * sim->dt;
             cronos::AdjNext nx;
             if (k > 0) {
-                nx.x = R.seg_x + (size_t)(k - 1) * n;
-                nx.vstar = R.seg_vs + (size_t)(k - 1) * 3 * n;
+                nx.x = R.seg_x[p] + (size_t)(k - 1) * n;
+                nx.vstar = R.seg_vs[p] + (size_t)(k - 1) * 3 * n;
                 nx.vb1 = R.vb[cur ^ 1];
                 nx.w = R.w[wc ^ 1];
                 nx.vb0 = R.vb[cur];
                 nx.xbl = R.xbl[wc ^ 1];
             }
-            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], R.sens,
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x[p] + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], R.sens,
                                               std::cos(sim->omega * t), std::sin(sim->omega * t), st,
-                                              sim->actuated ? R.seg_f + (size_t)k * fs : nullptr, sim->p, nx));
+                                              sim->actuated ? R.seg_f[p] + (size_t)k * fs : nullptr, sim->p, nx));
             cur ^= 1;
             if (k > 0) wc ^= 1;
         }
+        HIP_TRY(hipEventRecord(done_rev[p], st));
     }
     return CRONOS_OK;
 }
@@ -1350,7 +1396,8 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     if (sim->use_graph) {
         const std::vector<double> key = {(double)R.n0, (double)R.T, (double)R.K, (double)R.nseg,
                                          (double)(sim->cycles >> 32), (double)(sim->cycles & 0xFFFFFFFFull), sim->omega,
-                                         (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x, (double)(uintptr_t)R.seg_f,
+                                         (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x[0], (double)(uintptr_t)R.seg_x[1],
+                                         (double)(uintptr_t)R.seg_f[0], (double)(uintptr_t)R.seg_f[1],
                                          (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens};
         if (!R.bwd_graph || R.bwd_key != key) {
             if (R.bwd_graph) {
