@@ -20,6 +20,9 @@ namespace {
 
 constexpr int kMaxWaves = 16;
 constexpr size_t kModesMaxLds = 150 * 1024;   // dynamic LDS of the staged apply kernel (of 160 KiB)
+// workgroups of the vector kernels of an iteration: each workgroup first sums the previous
+// kernel's partials, so fewer of them (each thread taking several masses) cost fewer sums
+constexpr int kModesVecGroups = 512;
 
 __device__ __forceinline__ double wave_add(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -228,9 +231,8 @@ __global__ void __launch_bounds__(256) modes_update_kernel(const double* __restr
     __shared__ double red[kMaxWaves + 1];
     const double al = sum_parts(apart, n_apart, red);
     const double bp = k > 0 ? beta[k - 1] : 0.0;
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     double nn = 0.0;
-    if (i < n) {
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x)) {
         for (int c = 0; c < 3; ++c) {
             const double w = y[3 * i + c] - al * q[3 * i + c] - bp * qw[3 * i + c];
             qw[3 * i + c] = w;
@@ -249,8 +251,7 @@ __global__ void __launch_bounds__(256) modes_scale_kernel(const double* __restri
     __shared__ double red[kMaxWaves + 1];
     const double b = sqrt(sum_parts(part, n_part, red));
     const double inv = b > 0.0 ? 1.0 / b : 0.0;
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n)
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x))
         for (int c = 0; c < 3; ++c) w[3 * i + c] *= inv;
     if (k >= 0 && blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
 }
@@ -281,11 +282,12 @@ hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepPara
         hipLaunchKernelGGL(modes_apply_kernel, dim3((unsigned)d.nblk), dim3(d.block), 0, st, a, q, m.y, m.part_a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(modes_update_kernel, dim3(g), dim3(256), 0, st, m.part_a, (int)d.nblk, m.y, q, qw, m.alpha,
+    const int gv = std::min(g, kModesVecGroups);   // part_u holds g >= gv partials
+    hipLaunchKernelGGL(modes_update_kernel, dim3(gv), dim3(256), 0, st, m.part_a, (int)d.nblk, m.y, q, qw, m.alpha,
                        m.beta, k, m.part_u, n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(modes_scale_kernel, dim3(g), dim3(256), 0, st, m.part_u, g, qw, m.beta, k, n);
+    hipLaunchKernelGGL(modes_scale_kernel, dim3(gv), dim3(256), 0, st, m.part_u, gv, qw, m.beta, k, n);
     return hipGetLastError();
 }
 
