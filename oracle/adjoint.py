@@ -29,13 +29,16 @@ def rollout_loss(sys: P.System, x0, v0, n0: int, T: int, loss_w) -> float:
     return float((loss_w * x).sum())
 
 
-def rollout_grad(sys: P.System, x0, v0, n0: int, T: int, loss_w):
-    """Returns (loss, dL/dphase, dL/damp, dL/dx0, dL/dv0)."""
+def rollout_grad(sys: P.System, x0, v0, n0: int, T: int, loss_w, state_round=None):
+    """Returns (loss, dL/dphase, dL/damp, dL/dx0, dL/dv0).  state_round (optional) is applied to
+    every state of the forward rollout before it is stored and stepped on (e.g. rounding to
+    FP32, to measure how far a trajectory stored in FP32 moves the gradient)."""
+    rnd = state_round if state_round is not None else (lambda a: a)
     xs, vs = [np.array(x0, float)], [np.array(v0, float)]
     for n in range(T):
         x, v = P.step(sys, xs[-1], vs[-1], n0 + n)
-        xs.append(x)
-        vs.append(v)
+        xs.append(rnd(x))
+        vs.append(rnd(v))
     loss = float((loss_w * xs[-1]).sum())
 
     N = sys.n
