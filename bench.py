@@ -32,16 +32,32 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cantilever_400x40x40.
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_09334_amd", "csrc", "kernels.hip")
 
 
-def algorithmic_bytes(n_masses: int, n_springs: int, actuated: bool = False, batched: bool = False) -> int:
-    """Compulsory HBM traffic of one step of the per-mass CSR method: per mass read x, v and
-    write x, v (48 B), 1/m (4 B), a row offset (4 B); per spring two incidences of
-    (neighbour, k, L0) = 24 B; +2 B per spring when actuated, +4 B per mass when batched."""
+def formula_bytes(n_masses: int, n_springs: int, actuated: bool = False, batched: bool = False) -> int:
+    """HBM traffic of one step of a per-mass CSR method with explicit incidences: per mass
+    read x, v and write x, v (48 B), 1/m (4 B), a row offset (4 B); per spring two incidences
+    of (neighbour, k, L0) = 24 B; +2 B per spring when actuated, +4 B per mass when batched.
+    The step kernel's own encodings move less (see kernel_bytes)."""
     b = 56 * n_masses + 24 * n_springs
     if actuated:
         b += 2 * n_springs
     if batched:
         b += 4 * n_masses
     return b
+
+
+# bytes per incidence of each step form's entry stream: 16-bit words (neighbour slot and
+# (k, L0) pair index), 32-bit words, explicit (16-bit slot + FP32 k and L0; + a 16-bit
+# factor index when actuated), split (32-bit entry + a 4-byte record per spring end held)
+ENTRY_BYTES = {"narrow": 2, "table": 4, "explicit": 10, "split": 6, "resident": 4}
+
+
+def kernel_bytes(n_masses: int, n_springs: int, form: str, actuated: bool = False) -> int:
+    """Compulsory HBM bytes of one launch of the step kernel in its entry encoding: per mass
+    read and write x (float4: position and 1/m, 16 + 16 B) and v (12 + 12 B) and the lane's
+    2-byte mass index (58 B); per spring its two incidence entries.  Slice padding, halo
+    re-reads and the parameter table are overhead, not counted."""
+    per_inc = ENTRY_BYTES[form] + (2 if actuated and form == "explicit" else 0)
+    return 58 * n_masses + 2 * per_inc * n_springs
 
 
 def kernel_source_hash() -> str:
@@ -220,10 +236,29 @@ def frequency_bench(args) -> dict:
                      "ratio": f_sim / f_eb, "steps": n_samples * every})
         sim.close()
         print(f"frequency: {nx}x{ny}x{nz} f_sim {f_sim:.4f} Hz, EB {f_eb:.4f} Hz", file=sys.stderr, flush=True)
+    # static tip deflection of the 400 x 40 x 40 beam under a small load (tip deflection L/1000),
+    # relaxed with velocity damping that critically damps the first mode, against w L^4 / (8 E I)
+    w = W.cantilever(400, 40, 40, youngs=E, spacing=a)
+    Lb, H = 399 * a, 39 * a
+    g = 1e-3 * Lb * E * H ** 2 / (1.5 * rho * Lb ** 4)
+    w1 = K1 ** 2 * math.sqrt(E * H ** 2 / 12.0 / (rho * Lb ** 4))
+    stream = torch.cuda.Stream()
+    sim, lat, x0 = PR.create(w, stream=stream.cuda_stream, gravity=(0.0, 0.0, -g), damping=2.0 * w1 * w.dt)
+    tip = lat.coords[:, 0] == lat.coords[:, 0].max()
+    t0 = time.perf_counter()
+    CR.cronos_step(sim, int(round(6.0 / w.dt)))
+    xg, _, _ = CR.cronos_read_state(sim)
+    t_defl = time.perf_counter() - t0
+    sim.close()
+    defl = float(-(xg[tip, 2] - x0[tip, 2]).mean())
+    d_eb = 1.5 * rho * g * Lb ** 4 / (E * H ** 2)
+    deflection = {"nodes": [400, 40, 40], "g_eff": g, "tip_deflection_m": defl, "euler_bernoulli_m": d_eb,
+                  "ratio": defl / d_eb, "steps": int(round(6.0 / w.dt)), "seconds": t_defl}
+    print(f"frequency: 400x40x40 tip deflection {defl:.4e} m, EB {d_eb:.4e} m", file=sys.stderr, flush=True)
     return {"metric": "simulated / Euler-Bernoulli first frequency", "value": float(np.mean([r["ratio"] for r in rows])),
             "unit": "ratio", "higher_is_better": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "cantilever_sweep", "youngs": E, "density": rho, "spacing": a},
-            "beams": rows, "sim_seconds": t_sim, "steps": steps_total}
+            "beams": rows, "sim_seconds": t_sim, "steps": steps_total, "tip_deflection": deflection}
 
 
 def modes_bench(args) -> dict:
@@ -283,6 +318,56 @@ def spectral_peak(z, h: float) -> float:
     la, lb, lc = np.log(mag[k - 1:k + 2] + 1e-300)
     off = 0.5 * (la - lc) / (la - 2.0 * lb + lc) if la - 2.0 * lb + lc != 0.0 else 0.0
     return (k + off) / (n * h)
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of the MI355X
+
+
+def mlp_flops(sizes, rows: int) -> float:
+    """Matrix-product flops of one training step of the perceptron over `rows` rows: forward
+    Z = H W (2 rows K N per layer), weight gradient H^T dZ (the same) and back-propagation
+    dZ W^T (the same, except into the first layer's input)."""
+    per = [2.0 * rows * sizes[l] * sizes[l + 1] for l in range(len(sizes) - 1)]
+    return 3.0 * sum(per) - per[0]
+
+
+def mlp_bench(args) -> dict:
+    """Surrogate network training throughput on synthetic data of the surrogate's shapes: 96
+    inputs, three hidden layers of `width`, 3 outputs, minibatches of 1024 rows, `epochs`
+    epochs over `mlp_rows` rows; the matrix-product rate against the BF16 MFMA peak."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2207_09334_amd import cronos as CR
+
+    sizes = (96, args.width, args.width, args.width, 3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(args.mlp_rows, sizes[0])).astype(np.float32)
+    T = np.tanh(X[:, :3] + 0.1 * X[:, 3:6] * X[:, 6:9]).astype(np.float32)
+    batch = 1024
+    net = CR.cronos_mlp_create(W.mlp_init(4, sizes), max_rows=batch)
+    CR.cronos_mlp_train(net, X[:batch * 4], T[:batch * 4], batch=batch, epochs=1, lr=1e-3, seed=1)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = CR.cronos_mlp_train(net, X, T, batch=batch, epochs=args.epochs, lr=1e-3, seed=2)
+    sec = time.perf_counter() - t0
+    steps = args.epochs * ((args.mlp_rows + batch - 1) // batch)
+    flops = args.epochs * mlp_flops(sizes, args.mlp_rows)
+    xf = rng.normal(size=(65536, sizes[0])).astype(np.float32)
+    CR.cronos_mlp_forward(net, xf[:batch])
+    t1 = time.perf_counter()
+    CR.cronos_mlp_forward(net, xf)
+    fsec = time.perf_counter() - t1
+    tf = flops / sec / 1e12
+    return {"metric": "surrogate MLP training matrix-product rate", "value": tf, "unit": "TFLOP/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"mlp_96x{args.width}x{args.width}x{args.width}x3", "rows": args.mlp_rows,
+                       "batch": batch, "epochs": args.epochs},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / MFMA_BF16_PEAK_TFLOPS},
+            "train_seconds": sec, "us_per_minibatch": sec / steps * 1e6, "last_epoch_loss": loss,
+            "forward_rows_per_s": len(xf) / fsec}
 
 
 def surrogate_bench(args) -> dict:
@@ -377,8 +462,13 @@ def surrogate_bench(args) -> dict:
         "rms_rel_error_constant_predictor": err_mean, "simulator_noise_floor": noise_floor,
         "train_loss": sur.train_loss,
         "train_seconds": sur.train_seconds, "flagged": int(flagged.sum()), "simulated_after_screen": int(len(chosen)),
-        "top5pct_overlap": len(true_top & pred_top) / k,
+        "top5pct_overlap": len(true_top & pred_top) / k, "top5pct_overlap_random": k / n_cand,
         "best_true_x_in_screened": float(Dte[chosen, 0].max()), "best_true_x_overall": float(Dte[:, 0].max()),
+        # the screened quantity alone: forward (x) displacement
+        "x_rms_rel_error": float(np.sqrt(((pred[:, 0] - Dte[:, 0]) ** 2).mean() / (Dte[:, 0] ** 2).mean())),
+        "x_rms_rel_error_constant_predictor": float(np.sqrt(((Dtr[:, 0].mean() - Dte[:, 0]) ** 2).mean() /
+                                                            (Dte[:, 0] ** 2).mean())),
+        "x_spearman": float(np.corrcoef(np.argsort(np.argsort(pred[:, 0])), np.argsort(np.argsort(Dte[:, 0])))[0, 1]),
     }
 
 
@@ -401,7 +491,8 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--nx", type=int, default=400)
     ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "candidate", "surrogate",
-                                           "adjoint", "frequency", "modes"), default="cantilever")
+                                           "adjoint", "frequency", "modes", "mlp"), default="cantilever")
+    ap.add_argument("--mlp-rows", type=int, default=196_608, help="mlp: training rows")
     ap.add_argument("--sweep", type=lambda t: [tuple(int(v) for v in b.split("x")) for b in t.split(",")],
                     default=[(200, 40, 40), (300, 40, 40), (400, 40, 40), (400, 40, 30), (400, 40, 20), (400, 20, 40)],
                     help="frequency, modes: beams as NXxNYxNZ node counts, comma separated")
@@ -437,6 +528,9 @@ def main(argv=None):
         return
     if args.workload == "adjoint":
         print(json.dumps(adjoint_bench(args)), flush=True)
+        return
+    if args.workload == "mlp":
+        print(json.dumps(mlp_bench(args)), flush=True)
         return
     if args.workload == "frequency":
         print(json.dumps(frequency_bench(args)), flush=True)
@@ -514,8 +608,9 @@ def main(argv=None):
 
     sec_per_step = ms / 1e3 / args.steps
     value = S / sec_per_step
-    b_step = algorithmic_bytes(N, S, actuated=actuated, batched=batched)
-    achieved = b_step / sec_per_step / 1e9
+    b_kernel = kernel_bytes(N, S, launch["step_form"], actuated=actuated)
+    b_formula = formula_bytes(N, S, actuated=actuated, batched=batched)
+    achieved = b_kernel / sec_per_step / 1e9
     prof = profile_record(w.name, launch)
     traffic = float(prof["hbm_bytes_per_launch"]) if prof else None
     out = {
@@ -530,7 +625,10 @@ def main(argv=None):
                    "integrator": args.integrator},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": b_step},
+                     "algorithmic_bytes_per_launch": b_kernel,
+                     "traffic_frac": None if traffic is None else traffic / sec_per_step / 1e9 / HBM_PEAK_GBS,
+                     "formula_bytes_per_launch": b_formula,
+                     "formula_frac": b_formula / sec_per_step / 1e9 / HBM_PEAK_GBS},
     }
     if copy_gbs is not None:
         out["roofline"]["copy_kernel_gbs"] = copy_gbs

@@ -155,6 +155,18 @@ cronos_status cronos_candidate_points(const double* size, int64_t n_points, int3
  * (arguments, non-finite points, S > max_springs > 0), ENOMEM. */
 cronos_status cronos_cutoff_springs(int64_t n_points, const double* points, double cutoff, int64_t max_springs,
                                     int32_t* ends, int64_t* n_springs);
+/* Physical parameters of a point lattice (section "Generating a Lattice": masses come from the
+ * nodes and springs from the edges; the paper's starting point is 0.1 kg per mass and a spring
+ * constant of 10,000 scaled inversely to the spring's length).  For every spring s = (i, j) of
+ * ends [S][2]: rest[s] = |p_j - p_i|, its initial length, formed as sqrt((dx*dx + dy*dy) + dz*dz)
+ * in FP64; k[s] = (k_ref * length_ref) / rest[s].  For every point: mass[i] = mass_per_point;
+ * pinned[i] = 1 if points[i][pin_axis] < pin_below, else 0 (pin_axis = -1: none fixed).
+ * Outputs are caller-owned ([S], [S], [N], [N]); a NULL output is skipped.  Host-only.
+ * Errors: EINVAL (an end out of range or i == j, a zero-length spring, k_ref, length_ref or
+ * mass_per_point not positive, pin_axis outside [-1, 2]). */
+cronos_status cronos_point_params(int64_t n_points, const double* points, int64_t n_springs, const int32_t* ends,
+                                  double k_ref, double length_ref, double mass_per_point, int32_t pin_axis,
+                                  double pin_below, double* k, double* rest, double* mass, uint8_t* pinned);
 
 typedef struct cronos_layout_t* cronos_layout;
 
@@ -238,16 +250,26 @@ typedef struct {
     int32_t pad_;
 } cronos_diag;
 
-/* Validate the inputs, renumber (as cronos_layout_build), copy everything to device memory
- * of desc->device and bind desc->stream.  Unless CRONOS_ALLOW_UNSTABLE is set, estimates the
+/* The system of section "Method", "Mass-Spring Force Distribution": point masses x_i, v_i, m_i
+ * joined by springs (i, j, k_ij, l0_ij) with the forces of eqs. (1)-(2) (gravity and a
+ * constant f_ext included), integrated by eqs. (3)-(4) at time step dt ("Time Integration
+ * Schemes"; CRONOS_VERLET: eqs. (5)-(6)); with the constraints of "Generating a Lattice" (fixed
+ * masses, a contact plane, whose friction Appendix A names) and the velocity damping of the
+ * Euler-Bernoulli tests.  The lattice then "is copied to GPU memory" (end of "Generating a
+ * Lattice"): validate the inputs, renumber (as cronos_layout_build), copy everything to device
+ * memory of desc->device and bind desc->stream.  All input arrays stay the caller's.  The
+ * step's HIP graphs are captured here, so no cronos_step call pays for them.  Unless CRONOS_ALLOW_UNSTABLE is set, estimates the
  * largest natural frequency w of the rest-state system (plus the contact plane's stiffness)
  * and fails with EUNSTABLE when w * dt >= 2, where symplectic Euler diverges.
  * Errors: EINVAL, ENOMEM, EDEVICE, EUNSTABLE. */
 cronos_status cronos_create(const cronos_desc* desc, cronos_sim* out);
 void cronos_destroy(cronos_sim sim);
 
-/* Actuation (rest length of a spring of group g in body b at t_n = n dt:
- * L0 (1 + amp[b*G+g] sin(2 pi freq_hz t_n + phase[b*G+g]))).  phase, amp: host
+/* Actuated springs (section "Method": springs individually rigid, actuated or functionally
+ * parameterised, figure of a mass and its springs; "Multi-Materials and Self-Actuation":
+ * actuation by changing volumetric properties over time).  The paper gives no law; this one:
+ * the rest length of a spring of group g in body b at t_n = n dt is
+ * L0 (1 + amp[b*G+g] sin(2 pi freq_hz t_n + phase[b*G+g])).  phase, amp: host
  * [n_bodies*n_groups], copied (held in FP32 on the device; the period fraction frac(n f dt)
  * is formed exactly in 64-bit fixed point, so the phase stays within ~1e-7 rad of its
  * FP64 value at any step).  Errors: EINVAL (sim has no groups, non-finite values). */
@@ -260,11 +282,18 @@ cronos_status cronos_set_actuation(cronos_sim sim, const double* phase, const do
  * fixed masses held.  Errors: EINVAL (n_steps < 0), EDEVICE. */
 cronos_status cronos_step(cronos_sim sim, int64_t n_steps);
 
-/* Wait for the stream, then copy positions and velocities out (input order, widened to
- * double).  x, v: [N][3] or NULL.  Errors: EDEVICE. */
+/* The GPU-to-CPU direction of the state sync of section "Parallel Algorithm", paragraph "GPU
+ * Implementation": wait for the stream, then copy positions and velocities out (input order,
+ * widened to double; the device's FP32 values exactly).  x, v: [N][3] caller-owned or NULL
+ * (skipped); *step receives the step counter n (NULL skips).  Errors: EINVAL (NULL handle),
+ * EDEVICE. */
 cronos_status cronos_read_state(cronos_sim sim, double* x, double* v, int64_t* step);
 
-/* Overwrite the state (input order; rounded to FP32) and the step counter n. */
+/* The CPU-to-GPU direction of the same sync: overwrite the state (input order; rounded to
+ * FP32; fixed masses get v = 0) and the step counter n (the actuation time t_n).  A state read
+ * by cronos_read_state from a simulation created from the same inputs continues bit for bit
+ * (checkpoint and resume), except under CRONOS_VERLET, which restarts from (x, v) with the
+ * half kick of eq. (5).  Errors: EINVAL (NULL handle, step < 0, non-finite x), EDEVICE. */
 cronos_status cronos_set_state(cronos_sim sim, const double* x, const double* v, int64_t step);
 
 /* Total force of eq. (2) plus the contact normal force on every mass at the current state

@@ -103,6 +103,7 @@ _SIGS = {
     "cronos_get_layout": (C.c_int, [_p] * 6),
     "cronos_candidate_points": (C.c_int, [_p, _i64, _i32, _i32, C.c_uint64, _p]),
     "cronos_cutoff_springs": (C.c_int, [_i64, _p, _f64, _i64, _p, C.POINTER(_i64)]),
+    "cronos_point_params": (C.c_int, [_i64, _p, _i64, _p, _f64, _f64, _f64, _i32, _f64, _p, _p, _p, _p]),
     "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
                                        C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
@@ -303,6 +304,19 @@ def cronos_cutoff_springs(points, cutoff: float) -> np.ndarray:
     ends = np.empty((count.value, 2), np.int32)
     _check(_lib.cronos_cutoff_springs(len(pts), _ptr(pts), float(cutoff), len(ends), _ptr(ends), C.byref(count)))
     return ends
+
+
+def cronos_point_params(points, ends, k_ref: float, length_ref: float, mass_per_point: float, pin_axis: int = -1,
+                        pin_below: float = 0.0) -> tuple:
+    """Returns (k [S], rest [S], mass [N], pinned [N] uint8) of a point lattice."""
+    pts = _arr(points, np.float64, (-1, 3))
+    e = _arr(ends, np.int32, (-1, 2))
+    k, rest = np.empty(len(e)), np.empty(len(e))
+    mass, pinned = np.empty(len(pts)), np.empty(len(pts), np.uint8)
+    _check(_lib.cronos_point_params(len(pts), _ptr(pts), len(e), _ptr(e), float(k_ref), float(length_ref),
+                                    float(mass_per_point), int(pin_axis), float(pin_below), _ptr(k), _ptr(rest),
+                                    _ptr(mass), _ptr(pinned)))
+    return k, rest, mass, pinned
 
 
 def cronos_launch_config(sim: Sim) -> dict:

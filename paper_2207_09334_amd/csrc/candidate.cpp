@@ -198,3 +198,32 @@ extern "C" cronos_status cronos_cutoff_springs(int64_t n_points, const double* p
     }
     return CRONOS_OK;
 }
+
+extern "C" cronos_status cronos_point_params(int64_t n_points, const double* points, int64_t n_springs,
+                                             const int32_t* ends, double k_ref, double length_ref,
+                                             double mass_per_point, int32_t pin_axis, double pin_below, double* k,
+                                             double* rest, double* mass, uint8_t* pinned) {
+    cronos::clear_error();
+    if (n_points < 1 || !points || n_springs < 0 || (n_springs > 0 && !ends) || !(k_ref > 0.0) ||
+        !(length_ref > 0.0) || !(mass_per_point > 0.0) || pin_axis < -1 || pin_axis > 2 ||
+        !std::isfinite(k_ref * length_ref) || !std::isfinite(mass_per_point))
+        return cronos::fail(CRONOS_EINVAL, "point_params: bad arguments");
+    for (int64_t s = 0; s < n_springs; ++s) {
+        const int64_t i = ends[2 * s], j = ends[2 * s + 1];
+        if (i < 0 || j < 0 || i >= n_points || j >= n_points || i == j)
+            return cronos::fail(CRONOS_EINVAL, "point_params: spring %lld has bad ends", (long long)s);
+        const double dx = points[3 * j] - points[3 * i], dy = points[3 * j + 1] - points[3 * i + 1],
+                     dz = points[3 * j + 2] - points[3 * i + 2];
+        // the spring's initial length is its rest length; its stiffness scales inversely to it
+        const double len = std::sqrt((dx * dx + dy * dy) + dz * dz);
+        if (!(len > 0.0) || !std::isfinite(len))
+            return cronos::fail(CRONOS_EINVAL, "point_params: spring %lld has zero or non-finite length", (long long)s);
+        if (rest) rest[s] = len;
+        if (k) k[s] = (k_ref * length_ref) / len;
+    }
+    for (int64_t i = 0; i < n_points; ++i) {
+        if (mass) mass[i] = mass_per_point;
+        if (pinned) pinned[i] = pin_axis >= 0 && points[3 * i + pin_axis] < pin_below ? 1 : 0;
+    }
+    return CRONOS_OK;
+}

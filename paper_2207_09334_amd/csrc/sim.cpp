@@ -257,11 +257,14 @@ cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
     return CRONOS_OK;
 }
 
-cronos_status ensure_graph(cronos_sim_t* s) {
-    if (s->graph[s->cur]) return CRONOS_OK;
+// Captures kGraphSteps launches starting from position buffer `par` as one HIP graph (if not
+// already held).  Capture only records the launches; nothing runs.
+cronos_status ensure_graph(cronos_sim_t* s, int par) {
+    if (s->graph[par]) return CRONOS_OK;
     hipGraph_t g = nullptr;
+    const int cur0 = s->cur;
+    s->cur = par;
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    int cur0 = s->cur;
     cronos_status st = enqueue_plain(s, kGraphSteps);
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     s->cur = cur0;
@@ -270,9 +273,21 @@ cronos_status ensure_graph(cronos_sim_t* s) {
         return st;
     }
     if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&s->graph[cur0], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->graph[par], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        s->graph[par] = nullptr;
+        return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return CRONOS_OK;
+}
+
+// Both parities' graphs, built ahead of the first cronos_step (at creation and whenever the
+// parameters they capture change), so that no step call pays for capture and instantiation.
+cronos_status prepare_graphs(cronos_sim_t* s) {
+    if (!s->use_graph || !s->stream || s->d.resident) return CRONOS_OK;
+    TRY(ensure_graph(s, 0));
+    TRY(ensure_graph(s, 1));
     return CRONOS_OK;
 }
 
@@ -874,6 +889,11 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     sim->lay.nbr_local.shrink_to_fit();
     sim->lay.entry_csr.clear();
     sim->lay.entry_csr.shrink_to_fit();
+    if ((st = prepare_graphs(sim)) != CRONOS_OK) {
+        free_device(sim);
+        delete sim;
+        return st;
+    }
     *out = sim;
     return CRONOS_OK;
 }
@@ -913,9 +933,14 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
             (void)hipGraphExecDestroy(gr);
             gr = nullptr;
         }
+    if (sim->ro.bwd_graph) {      // so did the reverse sweep's recompute (p.safe among them)
+        (void)hipGraphExecDestroy(sim->ro.bwd_graph);
+        sim->ro.bwd_graph = nullptr;
+        sim->ro.bwd_key.clear();
+    }
     sim->h_phase.assign(phase, phase + m);
     sim->h_amp.assign(amp, amp + m);
-    return CRONOS_OK;
+    return prepare_graphs(sim);
 }
 
 extern "C" cronos_status cronos_step(cronos_sim sim, int64_t n_steps) {
@@ -949,7 +974,7 @@ extern "C" cronos_status cronos_step(cronos_sim sim, int64_t n_steps) {
         --left;
     }
     if (sim->use_graph && sim->stream && left >= kGraphSteps) {
-        TRY(ensure_graph(sim));
+        TRY(ensure_graph(sim, sim->cur));
         while (left >= kGraphSteps) {
             HIP_TRY(hipGraphLaunch(sim->graph[sim->cur], sim->stream));
             left -= kGraphSteps;

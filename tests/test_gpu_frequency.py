@@ -45,3 +45,32 @@ def test_simulated_first_frequency_matches_eigen_prediction():
         f"{len(cross)} crossings")
     assert len(cross) >= 5
     assert 2 * math.pi / period == pytest.approx(w_d, rel=2e-3)
+
+
+def test_cantilever_tip_deflection_matches_euler_bernoulli():
+    """Section "Euler-Bernoulli Beam Tests" at full size on the device: the 400x40x40-node
+    cantilever (L = 1.995 m, square section H = 0.195 m, E = 1 MPa, rho = 1000 kg/m^3, x = 0
+    face fixed) under a small body load g_eff chosen for a tip deflection of L / 1000 (small
+    deflection, where the theory holds; the configured full gravity would sag it six times
+    its length), relaxed with velocity damping that critically damps the first mode (every
+    mode then decays as exp(-w1 t)) for 6 s: the mean vertical displacement of the free end
+    face matches w L^4 / (8 E I) = 1.5 rho g L^4 / (E H^2) within 3%."""
+    w = W.cantilever()
+    nx = 400
+    a, E, rho = w.spacing, 1.0e6, 1000.0
+    Lb, H = (nx - 1) * a, 39 * a
+    g = 1e-3 * Lb * E * H ** 2 / (1.5 * rho * Lb ** 4)
+    delta_eb = 1.5 * rho * g * Lb ** 4 / (E * H ** 2)
+    w1 = 1.8751040687 ** 2 * math.sqrt(E * H ** 2 / 12.0 / (rho * Lb ** 4))
+    damp = 2.0 * w1 * w.dt
+    say(f"case: cantilever 400x40x40 tip deflection, g_eff {g:.4e} m/s^2, damping {damp:.3e} per step")
+    sim, lat, x0 = PR.create(w, gravity=(0.0, 0.0, -g), damping=damp)
+    tip = lat.coords[:, 0] == lat.coords[:, 0].max()
+    steps = int(round(6.0 / w.dt))
+    for _ in range(10):
+        CR.cronos_step(sim, steps // 10)
+    xg, vg, _ = CR.cronos_read_state(sim)
+    defl = float(-(xg[tip, 2] - x0[tip, 2]).mean())
+    say(f"  tip deflection {defl:.6e} m, Euler-Bernoulli {delta_eb:.6e} m, ratio {defl / delta_eb:.4f}; "
+        f"max |v| {np.abs(vg).max():.2e} m/s")
+    assert defl / delta_eb == pytest.approx(1.0, abs=0.03)

@@ -71,7 +71,9 @@ def test_forces_quadruped_actuated():
 
 
 def test_forces_cantilever_full_size():
-    """640k masses / 8.0M springs, the benchmark's launch configuration (256-mass workgroups)."""
+    """640k masses / 8.0M springs through the force hook (cronos_eval_forces: the explicit
+    per-entry gather of forces_kernel); the benchmarked step kernel itself is held to the same
+    bar in test_step_forces_cantilever_full_size_benchmarked_form."""
     w = W.cantilever()
     say("case: cantilever 400x40x40 forces")
     lat, sys_, x0 = oracle_problem(w)
@@ -83,6 +85,71 @@ def test_forces_cantilever_full_size():
         e, en = force_error(CR.cronos_eval_forces(sim), sys_, xg, n * w.dt)
         say(f"  step {n}: force err {e:.3e} (normwise {en:.3e})")
         assert e <= F_TOL
+
+
+def _step_forces(sim, w, lat, xg, n):
+    """The total force of the device's own step at state (xg, v = 0), step n: one step from rest
+    with no contact and no damping gives v' = dt (f/m + g), so F = m v' / dt (m from the device's
+    FP32 1/m).  Fixed masses excluded."""
+    CR.cronos_set_state(sim, xg, np.zeros_like(xg), n)
+    CR.cronos_step(sim, 1)
+    _, v1, n1 = CR.cronos_read_state(sim)
+    assert n1 == n + 1
+    inv_m = (1.0 / lat.mass).astype(np.float32).astype(np.float64)
+    return (v1 / float(np.float32(w.dt))) / inv_m[:, None]
+
+
+def test_step_forces_cantilever_full_size_benchmarked_form():
+    """The benchmarked kernel at the benchmarked size: the 400x40x40 cantilever created with
+    the defaults (16-bit entries, 512-mass workgroups, HIP graphs), stepped 200 steps from rest
+    under gravity (a sagging, nearly relaxed lattice: elongations of ~1e-7 m, where the
+    elongation arithmetic matters), then one step from that state with v = 0: the step's own
+    total force m v'/dt on every free mass within 1e-5 of S_i of the oracle's, fed the device's
+    FP32 state and parameters."""
+    w = W.cantilever()
+    say("case: cantilever 400x40x40, benchmarked step form, step forces at step 200")
+    lat, sys_, x0 = oracle_problem(w)
+    sim, _, _ = PR.create(w, x0=x0)
+    cfg = CR.cronos_launch_config(sim)
+    say(f"  launch {cfg}")
+    assert cfg["step_form"] == "narrow" and cfg["block_masses"] == 512 and cfg["lanes_per_mass"] == 1
+    CR.cronos_step(sim, 200)
+    xg, _, n = CR.cronos_read_state(sim)
+    f_dev = _step_forces(sim, w, lat, xg, n)
+    s32 = as_f32(sys_)
+    f_ref = P.forces(s32, xg, n * w.dt)
+    S = force_scale(s32, xg, n * w.dt)
+    free = ~np.asarray(lat.pinned, bool)
+    err = np.linalg.norm(f_dev - f_ref, axis=1) / S
+    e = float(err[free].max())
+    _, length = P.spring_vectors(xg, s32.ends)
+    say(f"  step force err {e:.3e} (median {np.median(err[free]):.2e}); "
+        f"median |elongation| {np.median(np.abs(length - s32.rest)):.2e} m")
+    assert e <= F_TOL
+
+
+def test_cantilever_full_size_step_forms_bitwise_equal():
+    """The full cantilever in the benchmarked form (16-bit entries) against the 32-bit entries
+    and the explicit per-entry (k, L0) form at the same 512-mass workgroups: bitwise the same
+    states after 100 steps (the same per-spring arithmetic in the same order), so the
+    encodings and halo lists at this size (the 16-bit split of slot and pair bits) lose
+    nothing."""
+    w = W.cantilever()
+    say("case: cantilever 400x40x40, 100 steps: narrow / table / explicit, 512-mass workgroups")
+    lat = PR.build_lattice(w)
+    outs, forms = [], []
+    for flags in (0, CR.WIDE_ENTRIES, CR.NO_TABLE):
+        sim, _, _ = PR.create(w, lat=lat, flags=flags, block_masses=512)
+        forms.append(CR.cronos_launch_config(sim)["step_form"])
+        CR.cronos_step(sim, 100)
+        xg, vg, _ = CR.cronos_read_state(sim)
+        assert np.isfinite(xg).all()
+        outs.append((xg, vg))
+        sim.close()
+    say(f"  forms {forms}")
+    assert forms == ["narrow", "table", "explicit"]
+    for xg, vg in outs[1:]:
+        assert np.array_equal(xg, outs[0][0]) and np.array_equal(vg, outs[0][1])
 
 
 def test_one_step_consistency_cantilever_full_size():
@@ -159,6 +226,29 @@ def test_positions_quadruped_1000():
             assert e <= X_TOL
         else:
             assert e <= max(X_TOL, 10.0 * floor)
+
+
+def test_positions_quadruped_no_contact_1000():
+    """The actuated quadruped with the contact plane off (gravity on, damping as configured):
+    without contact the dynamics are not chaotic over 1000 steps, so the strict 1e-4 bar holds
+    at every 100th step; this separates the FP32 actuation factor and spring arithmetic (held
+    here) from the contact chaos that sets the FP32-state floor of the configured run."""
+    w = W.quadruped()
+    say("case: quadruped steps 0-1000, actuated, no contact plane")
+    lat, _, x0 = oracle_problem(w)
+    sys_ = P.system_from(lat, w, ground=False)
+    sim, _, _ = PR.create(w, x0=x0, ground=False, flags=CR.CHECK_LAYOUT)
+    x, v = x0.copy(), np.zeros_like(x0)
+    worst = 0.0
+    for n in range(0, 1000, 100):
+        x, v = P.run(sys_, x, v, n, 100)
+        CR.cronos_step(sim, 100)
+        xg, _, _ = CR.cronos_read_state(sim)
+        e = position_error(xg, x)
+        worst = max(worst, e)
+        say(f"  step {n + 100}: position err {e:.3e}")
+        assert e <= X_TOL
+    assert worst > 0.0
 
 
 def test_positions_cantilever_slab_1000():

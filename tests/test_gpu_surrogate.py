@@ -21,6 +21,20 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
+def _elem(a, b, axis=None):
+    """Elementwise error: max |a - b| over the elements, divided by max |b| (per column of a
+    2-D output when axis=0), the largest such ratio."""
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    scale = np.abs(b).max(axis=axis, keepdims=axis is not None)
+    return float((np.abs(a - b) / np.maximum(scale, 1e-300)).max())
+
+
+# Elementwise bars, about 10x the measured errors: FP32 accumulation against exact sums, and a
+# hidden activation now and then rounding to the neighbouring BF16 value
+Y_TOL = 1e-3
+G_TOL = 2e-3
+
+
 @pytest.mark.parametrize("rows", [1, 64, 200, 4096])
 def test_forward_matches_oracle(rows):
     params = W.mlp_init(4)
@@ -29,9 +43,9 @@ def test_forward_matches_oracle(rows):
     net = CR.cronos_mlp_create(params, max_rows=4096)
     y = CR.cronos_mlp_forward(net, X.astype(np.float32))
     ref, _ = M.forward(params, X.astype(np.float32).astype(np.float64), storage="bf16")
-    e = _rel(y, ref)
-    say(f"  rows {rows}: forward rel err {e:.2e}; max abs {np.abs(y - ref).max():.2e}")
-    assert e <= 1e-2
+    e, el = _rel(y, ref), _elem(y, ref, axis=0)
+    say(f"  rows {rows}: forward rel err {e:.2e}; elementwise {el:.2e}; max abs {np.abs(y - ref).max():.2e}")
+    assert e <= Y_TOL and el <= Y_TOL
     # without the storage model the gap is the BF16 rounding itself (~1e-2): the device does
     # not skip it
     assert _rel(y, M.forward(params, X, storage="fp64")[0]) <= 5e-2
@@ -46,20 +60,23 @@ def test_forward_beyond_max_rows_is_chunked():
     assert np.array_equal(y, CR.cronos_mlp_forward(net2, X.astype(np.float32)))
 
 
-def test_gradients_match_oracle():
+@pytest.mark.parametrize("rows", [300, 2048])
+def test_gradients_match_oracle(rows):
+    """300 rows: every product in one pass over K; 2048 rows: the weight-gradient products
+    split their K (the rows) into FP32 partials summed in a fixed order."""
     params = W.mlp_init(4)
     params = [p + 0.05 * np.random.default_rng(2).normal(size=p.shape) for p in params]
-    X, T = _data(300, seed=3)
-    net = CR.cronos_mlp_create(params, max_rows=512)
+    X, T = _data(rows, seed=3)
+    net = CR.cronos_mlp_create(params, max_rows=rows)
     loss, g = CR.cronos_mlp_loss_grad(net, X.astype(np.float32), T.astype(np.float32))
     lo, go = M.loss_and_grad(params, X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64),
                              storage="bf16")
     say(f"  loss dev {loss:.6e} oracle {lo:.6e}")
-    assert loss == pytest.approx(lo, rel=1e-2)
+    assert loss == pytest.approx(lo, rel=1e-4)
     for l in range(8):
-        e = _rel(g[l], go[l])
-        say(f"  grad {l}: rel err {e:.2e}")
-        assert e <= 2e-2
+        e, el = _rel(g[l], go[l]), _elem(g[l], go[l])
+        say(f"  grad {l} {np.shape(go[l])}: rel err {e:.2e}, elementwise {el:.2e}")
+        assert e <= G_TOL and el <= G_TOL
 
 
 def test_adam_step_matches_oracle():
@@ -135,3 +152,34 @@ def test_screening_pipeline_small():
     assert flags[0] and not flags[1:].any()
     chosen = SG.screen(sur.predict(far), flags, top_k=1)
     assert 0 in chosen
+
+
+def test_trained_network_gains_over_the_method_without_it():
+    """What the trained network adds: on robots it never saw in training (a pool of 256 random
+    -walk robots, 8 actuation draws each, 1000-step rollouts judged by the simulator), the
+    network's displacement error is far below that of the best prediction without it (the
+    training mean), and ranking candidates by its predicted forward displacement finds the
+    truly best ones far more often than a random screen of the same size would."""
+    from paper_2207_09334_amd import surrogate as SG
+    pool = SG.Pool(256, seed=4, steps=1000, lo=300, hi=3000)
+    Xs, Ds = zip(*[pool.draw(d) for d in range(8)])
+    pool.close()
+    X, D = np.concatenate(Xs), np.concatenate(Ds)
+    robot = np.tile(np.arange(256), 8)
+    train, held = robot < 224, robot >= 224
+    sur = SG.Surrogate(X[train], D[train], epochs=60, batch=128, max_rows=1024, width=256)
+    pred = sur.predict(X[held])
+    Dh = D[held]
+    err = SG.rms_relative_error(pred, Dh)
+    err0 = SG.rms_relative_error(np.broadcast_to(D[train].mean(axis=0), Dh.shape), Dh)
+    ex = float(np.sqrt(((pred[:, 0] - Dh[:, 0]) ** 2).mean() / (Dh[:, 0] ** 2).mean()))
+    ex0 = float(np.sqrt(((D[train][:, 0].mean() - Dh[:, 0]) ** 2).mean() / (Dh[:, 0] ** 2).mean()))
+    k = len(Dh) // 10
+    top_true = set(np.argsort(-Dh[:, 0], kind="stable")[:k].tolist())
+    top_pred = set(np.argsort(-pred[:, 0], kind="stable")[:k].tolist())
+    recall = len(top_true & top_pred) / k
+    say(f"  held-out: vector error {err:.3f} (constant predictor {err0:.3f}); x error {ex:.3f} "
+        f"(constant {ex0:.3f}); top-10% recall of x {recall:.2f} (random 0.10)")
+    assert err < 0.5 * err0
+    assert ex < 0.8 * ex0
+    assert recall >= 0.25

@@ -38,10 +38,15 @@ def test_screen_takes_top_k_and_every_flagged_candidate():
     assert SG.screen(np.zeros((3, 3)), np.zeros(3, bool), top_k=1).tolist() == [0]
 
 
-def test_algorithmic_bytes_of_the_headline_step():
-    # 56 B per mass + 24 B per spring: the cantilever 400x40x40
-    assert bench.algorithmic_bytes(640_000, 8_020_476) == 228_331_424
-    assert bench.algorithmic_bytes(10, 100, actuated=True, batched=True) == 56 * 10 + 26 * 100 + 4 * 10
+def test_byte_counts_of_the_headline_step():
+    # the explicit-incidence formula, 56 B per mass + 24 B per spring: the cantilever 400x40x40
+    assert bench.formula_bytes(640_000, 8_020_476) == 228_331_424
+    assert bench.formula_bytes(10, 100, actuated=True, batched=True) == 56 * 10 + 26 * 100 + 4 * 10
+    # the step kernel's 16-bit entries: 58 B per mass (x and v read and written, lane map) and
+    # 2 B per incidence, i.e. 4 B per spring
+    assert bench.kernel_bytes(640_000, 8_020_476, "narrow") == 58 * 640_000 + 4 * 8_020_476
+    assert bench.kernel_bytes(10, 100, "table", actuated=True) == 58 * 10 + 8 * 100
+    assert bench.kernel_bytes(10, 100, "explicit", actuated=True) == 58 * 10 + 24 * 100
 
 
 def test_profile_record_is_used_only_for_its_own_kernel_and_configuration(tmp_path, monkeypatch):

@@ -78,3 +78,30 @@ def test_native_candidate_rejects_bad_arguments():
         CR.cronos_candidate_points(SIZE, 10, k_nn=0)
     with pytest.raises(CR.CronosError):
         CR.cronos_cutoff_springs(np.zeros((3, 3)), -1.0)
+
+
+def test_native_point_params_bit_exact():
+    """The library's spring parameters of a point lattice (rest = initial length, k scaled
+    inversely to it, uniform mass, the x < pin_x end fixed) equal the oracle system's bit for
+    bit; every rest length is the pair's distance."""
+    pw = W.candidate_bar(600, size=SIZE, seed=3)
+    pts = OC.best_candidate_points(pw.size, pw.n_points, pw.n_candidates, pw.k_nn, pw.seed)
+    ends = OC.cutoff_springs(pts, pw.cutoff)
+    ref = OC.system(pw, pts, ends)
+    k, rest, mass, pinned = CR.cronos_point_params(pts, ends, pw.k_ref, pw.length_ref, pw.mass, pin_axis=0,
+                                                   pin_below=pw.pin_x)
+    np.testing.assert_array_equal(rest, ref.rest)
+    np.testing.assert_array_equal(k, ref.k)
+    np.testing.assert_array_equal(mass, ref.mass)
+    np.testing.assert_array_equal(pinned.astype(bool), ref.pinned)
+    assert 0 < pinned.sum() < len(pts)
+    np.testing.assert_allclose(rest, np.linalg.norm(pts[ends[:, 1]] - pts[ends[:, 0]], axis=1), rtol=1e-15)
+    np.testing.assert_allclose(k * rest, pw.k_ref * pw.length_ref, rtol=1e-15)
+    _, _, _, none = CR.cronos_point_params(pts, ends, 1.0, 1.0, 1.0)
+    assert not none.any()
+    with pytest.raises(CR.CronosError):
+        CR.cronos_point_params(pts, np.array([[0, 0]]), 1.0, 1.0, 1.0)
+    with pytest.raises(CR.CronosError):
+        CR.cronos_point_params(pts, np.array([[0, len(pts)]]), 1.0, 1.0, 1.0)
+    with pytest.raises(CR.CronosError):
+        CR.cronos_point_params(pts, ends, 1.0, 1.0, 1.0, pin_axis=3)
