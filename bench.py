@@ -48,15 +48,18 @@ def formula_bytes(n_masses: int, n_springs: int, actuated: bool = False, batched
 # bytes per incidence of each step form's entry stream: 16-bit words (neighbour slot and
 # (k, L0) pair index), 32-bit words, explicit (16-bit slot + FP32 k and L0; + a 16-bit
 # factor index when actuated), split (32-bit entry + a 4-byte record per spring end held)
-ENTRY_BYTES = {"narrow": 2, "table": 4, "explicit": 10, "split": 6, "resident": 4}
+ENTRY_BYTES = {"narrow": 2, "table": 4, "explicit": 10, "split": 6, "resident": 4, "grid": 0}
 
 
 def kernel_bytes(n_masses: int, n_springs: int, form: str, actuated: bool = False) -> int:
     """Compulsory HBM bytes of one launch of the step kernel in its entry encoding: per mass
     read and write x (float4: position and 1/m, 16 + 16 B) and v (12 + 12 B) and the lane's
-    2-byte mass index (58 B); per spring its two incidence entries.  Slice padding, halo
-    re-reads and the parameter table are overhead, not counted."""
+    2-byte mass index (58 B); per spring its two incidence entries.  The structured-box form
+    reads no incidence data and no lane map (56 B per mass).  Slice padding, halo re-reads,
+    halo lists and the parameter table are overhead, not counted."""
     per_inc = ENTRY_BYTES[form] + (2 if actuated and form == "explicit" else 0)
+    if form == "grid":   # no incidence data and no lane map: the state alone
+        return 56 * n_masses
     return 58 * n_masses + 2 * per_inc * n_springs
 
 
@@ -107,6 +110,49 @@ def cpu_baseline(workload, steps: int):
             "sample": f"{steps} FP64 NumPy steps of the full {workload.name} lattice "
                       f"({lat.n_masses} masses, {lat.n_springs} springs), single thread on {cpu_model()} "
                       f"({len(os.sched_getaffinity(0))} cores available), {dt:.1f} s"}
+
+
+def _cpu_worker(workload, steps, barrier, out):
+    """One process of the all-cores baseline: builds the oracle's lattice, takes one untimed
+    step, waits for the others, then times `steps` single-threaded steps."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lattice as L
+    from oracle import physics as P
+
+    lat = L.build(workload)
+    sys_ = P.system_from(lat, workload)
+    x, v = lat.x.copy(), np.zeros_like(lat.x)
+    with threadpool_limits(limits=1):
+        x, v = P.step(sys_, x, v, 0)
+        barrier.wait()
+        t0 = time.time()
+        x, v = P.run(sys_, x, v, 1, steps)
+        t1 = time.time()
+    out.put((t0, t1, lat.n_springs * steps))
+
+
+def cpu_baseline_all_cores(workload, steps: int, procs: int):
+    """The oracle on every host core at once: `procs` processes (started fresh, not forked
+    from this GPU process), each stepping its own copy of the workload single-threaded, all
+    timed over the same window; rate = all their spring-steps / (last end - first start)."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(procs), ctx.Queue()
+    ps = [ctx.Process(target=_cpu_worker, args=(workload, steps, barrier, out)) for _ in range(procs)]
+    for p in ps:
+        p.start()
+    res = [out.get() for _ in ps]
+    for p in ps:
+        p.join()
+    t0, t1 = min(r[0] for r in res), max(r[1] for r in res)
+    work = sum(r[2] for r in res)
+    return {"value": work / (t1 - t0), "unit": "spring-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} processes, each {steps} FP64 NumPy steps of its own copy of the full {workload.name} "
+                      f"lattice, single-threaded, on {cpu_model()}; {t1 - t0:.1f} s window"}
 
 
 def cpu_model() -> str:
@@ -485,10 +531,13 @@ def main(argv=None):
     ap.add_argument("--no-table", action="store_true", help="explicit per-entry (k, L0) instead of the table")
     ap.add_argument("--split", action="store_true", help="split step form (spring pass + gather pass)")
     ap.add_argument("--wide-entries", action="store_true", help="32-bit compact entries even where 16-bit ones fit")
+    ap.add_argument("--no-grid", action="store_true", help="never the structured-box step form")
     ap.add_argument("--integrator", choices=("euler", "verlet"), default="euler",
                     help="symplectic Euler (default) or Verlet, eqs. (5)-(6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="processes of the all-cores oracle baseline (0: the available cores, at most 16; 1: skip)")
     ap.add_argument("--nx", type=int, default=400)
     ap.add_argument("--workload", choices=("cantilever", "population", "quadruped", "cube", "candidate", "surrogate",
                                            "adjoint", "frequency", "modes", "mlp"), default="cantilever")
@@ -511,9 +560,10 @@ def main(argv=None):
     ap.add_argument("--dump", default="", help="surrogate: directory to save the data set to (npz)")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="also run one device-to-device copy of MIB MiB (read MIB, write MIB) before the "
-                         "timed steps, as the reference kernel for the HBM byte counters")
+    ap.add_argument("--calibrate-copy", type=int, default=2048, metavar="MIB",
+                    help="before the timed steps, time the library's streaming copy and read kernels over "
+                         "MIB MiB (the attainable-bandwidth reference and the reference kernel for the HBM "
+                         "byte counters); 0 skips")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for {args.gpus}); the step of one body would shard "
@@ -546,7 +596,7 @@ def main(argv=None):
     stream = torch.cuda.Stream()
     flags = ((CR.NO_GRAPH if args.no_graph else 0) | (CR.FAST_DIFF if args.fast_diff else 0) |
              (CR.NO_TABLE if args.no_table else 0) | (CR.SPLIT if args.split else 0) |
-             (CR.WIDE_ENTRIES if args.wide_entries else 0) |
+             (CR.WIDE_ENTRIES if args.wide_entries else 0) | (CR.NO_GRID if args.no_grid else 0) |
              (CR.VERLET if args.integrator == "verlet" else 0) | (CR.RESIDENT if args.resident else 0))
     if args.workload == "candidate":
         w = W.candidate_bar(args.points)
@@ -569,25 +619,11 @@ def main(argv=None):
     launch = CR.cronos_launch_config(sim)
     N, S = info["n_masses"], info["n_springs"]
 
-    copy_gbs = None
+    copy_gbs = read_gbs = None
     if args.calibrate_copy:
-        # a plain device-to-device copy of known size: the reference for the byte counters and
-        # the bandwidth a streaming kernel reaches on this device (best of 5)
-        src = torch.ones(args.calibrate_copy * (1 << 18), dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        best = None
-        with torch.cuda.stream(stream):
-            for _ in range(5):
-                e0.record(stream)
-                dst.copy_(src)
-                e1.record(stream)
-                e1.synchronize()
-                t = e0.elapsed_time(e1)
-                best = t if best is None else min(best, t)
-        torch.cuda.synchronize()
-        copy_gbs = 2.0 * src.numel() * 4 / (best / 1e3) / 1e9
-        del src, dst
+        # the library's plain streaming kernels over a buffer of known size: the bandwidth a
+        # hand-written HIP copy (read + write) and read pass reach on this device (best of 5)
+        copy_gbs, read_gbs = CR.cronos_stream_bandwidth(args.calibrate_copy << 20, reps=5)
     torch.cuda.synchronize()
     CR.cronos_step(sim, args.warmup)
     torch.cuda.synchronize()
@@ -632,7 +668,10 @@ def main(argv=None):
     }
     if copy_gbs is not None:
         out["roofline"]["copy_kernel_gbs"] = copy_gbs
+        out["roofline"]["read_kernel_gbs"] = read_gbs
         out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+        if traffic is not None:
+            out["roofline"]["traffic_frac_of_copy"] = traffic / sec_per_step / 1e9 / copy_gbs
     if prof and prof.get("valu_wave_instr_per_launch"):
         # the step's other ceiling: VALU issue, one wave64 instruction per cycle per CU
         # (non-packed FP32), from the committed SQ_INSTS_VALU count of this configuration
@@ -645,6 +684,9 @@ def main(argv=None):
     sim.close()
     if not args.no_cpu_baseline and lat is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        if args.cpu_procs != 1 and len(w.bodies) == 1:
+            procs = args.cpu_procs or min(16, len(os.sched_getaffinity(0)))
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w, max(1, args.cpu_steps // 2), procs)
     print(json.dumps(out), flush=True)
 
 

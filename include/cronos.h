@@ -67,6 +67,8 @@ typedef enum {
 #define CRONOS_WIDE_ENTRIES   0x200u /* keep 32-bit compact entries where 16-bit ones would fit
                                         (passive systems whose workgroup LDS slots and (k, L0)
                                         pairs fit in 16 bits; see CRONOS_FORM_NARROW)        */
+#define CRONOS_NO_GRID        0x400u /* never take the structured-box step form (CRONOS_FORM_GRID);
+                                        the other forms are chosen as without the flag        */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
                                         but a nearly relaxed spring within one spring length of
                                         a coordinate plane loses accuracy                     */
@@ -319,6 +321,21 @@ cronos_status cronos_eval_forces(cronos_sim sim, double* f);
 cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
                                          uint64_t seed, double* omega, int32_t* n_found, int32_t* iterations);
 
+/* cronos_natural_frequencies for callers that cannot allocate device memory (code under HIP
+   graph capture nearby, serving loops, harnesses that forbid hipMalloc): the same arguments,
+   computation and results, but every device buffer of the iteration (about 80 bytes per mass
+   plus 16 bytes per allowed Lanczos step) is carved from a fixed FP64 workspace of 64 MiB that
+   the library holds on each GPU it runs on until the process ends; no hipMalloc, hipFree or
+   other device allocation is made (the host-side tridiagonal work arrays are ordinary host
+   memory).  The workspace is looked up on the first call on a device.  Every call on one GPU
+   shares that workspace and overwrites it: calls that overlap on one GPU (from several
+   threads or streams) race and must be serialised by the caller.  EINVAL when
+   80 n + 16 max_iter bytes (n masses, plus alignment) exceed the workspace, as for
+   cronos_natural_frequencies otherwise. */
+cronos_status cronos_natural_frequencies_noalloc(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
+                                                 uint64_t seed, double* omega, int32_t* n_found,
+                                                 int32_t* iterations);
+
 /* The host step of cronos_natural_frequencies, exposed so it can be checked on its own: the
    `count` smallest eigenvalues theta[count] (increasing) of the symmetric tridiagonal matrix
    with diagonal a[k] and off-diagonal b[k-1] (NULL allowed when k = 1), by Sturm-sequence
@@ -332,6 +349,15 @@ cronos_status cronos_tridiag_smallest(int64_t k, const double* a, const double* 
  * Returns ESTATE (after filling out) when some body holds a non-finite value. */
 cronos_status cronos_diagnostics(cronos_sim sim, cronos_diag* out);
 
+/* Measurement reference (not part of the method): the bandwidth a plain streaming HIP kernel
+ * reaches on `device` -- a copy of `bytes` (read and write, counted twice) and a read-only
+ * pass over them, 16-byte accesses, best of `reps` timed launches after one warm-up (HIP
+ * events on a stream of its own).  Allocates and frees 2 x bytes of device memory.
+ * copy_gbs, read_gbs: GB/s (10^9 bytes/s), either may be NULL.  Errors: EINVAL (bytes < 1 MiB,
+ * reps < 1), ENOMEM, EDEVICE. */
+cronos_status cronos_stream_bandwidth(int32_t device, int64_t bytes, int32_t reps, double* copy_gbs,
+                                      double* read_gbs);
+
 /* Information on the simulation: masses, springs, bodies, groups, steps taken, block size. */
 cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs, int32_t* n_bodies,
                           int32_t* block_masses, int64_t* step);
@@ -344,6 +370,16 @@ cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs,
 #define CRONOS_FORM_RESIDENT 3  /* table form, the whole system in one workgroup, many steps per launch */
 #define CRONOS_FORM_NARROW   4  /* table form with 16-bit entries (passive systems whose LDS slot and
                                    pair index fit in 16 bits together): half the entry bytes        */
+#define CRONOS_FORM_GRID     5  /* structured box: the system is a full nx x ny x nz grid of masses
+                                   (dimensions multiples of 8, given by cronos_desc.grid) linked to
+                                   all 26 grid neighbours, passive, rest length fixed per direction
+                                   and k fixed per (direction, faces of the box the mass lies on);
+                                   one workgroup per aligned 8 x 8 x 8 cube, no incidence data read.
+                                   Chosen automatically for 512-mass workgroups with one lane per
+                                   mass unless CRONOS_NO_GRID, CRONOS_NO_TABLE, CRONOS_SPLIT,
+                                   CRONOS_WIDE_ENTRIES or CRONOS_RESIDENT is set.  Springs are summed
+                                   per mass in a fixed direction order (equal to the other forms'
+                                   sums to rounding)                                              */
 cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
                                    int32_t* step_form, int32_t* lanes_per_mass);
 

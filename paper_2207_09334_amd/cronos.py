@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcronos.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT, VERLET, RESIDENT, WIDE_ENTRIES = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80, 0x100, 0x200)
+NO_GRID = 0x400
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -97,7 +98,10 @@ _SIGS = {
     "cronos_diagnostics": (C.c_int, [_p, C.POINTER(Diag)]),
     "cronos_natural_frequencies": (C.c_int, [_p, _i32, _i32, _f64, C.c_uint64, _p, C.POINTER(_i32),
                                              C.POINTER(_i32)]),
+    "cronos_natural_frequencies_noalloc": (C.c_int, [_p, _i32, _i32, _f64, C.c_uint64, _p, C.POINTER(_i32),
+                                                     C.POINTER(_i32)]),
     "cronos_tridiag_smallest": (C.c_int, [_i64, _p, _p, _i64, _p, _p]),
+    "cronos_stream_bandwidth": (C.c_int, [_i32, _i64, _i32, C.POINTER(_f64), C.POINTER(_f64)]),
     "cronos_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
                               C.POINTER(_i64)]),
     "cronos_get_layout": (C.c_int, [_p] * 6),
@@ -286,7 +290,7 @@ def cronos_autotune(x0, mass, ends, k, rest, n_steps=20, **kw) -> dict:
     return cronos_create(x0, mass, ends, k, rest, _tune_steps=n_steps, **kw)
 
 
-FORMS = ("explicit", "table", "split", "resident", "narrow")
+FORMS = ("explicit", "table", "split", "resident", "narrow", "grid")
 
 
 def cronos_candidate_points(size, n_points: int, n_candidates: int = 100, k_nn: int = 4, seed: int = 0) -> np.ndarray:
@@ -372,6 +376,24 @@ def cronos_natural_frequencies(sim: Sim, n_modes: int = 2, max_iter: int = 200_0
     _check(_lib.cronos_natural_frequencies(sim.handle, n_modes, max_iter, tol, seed, _ptr(omega), C.byref(found),
                                            C.byref(iters)))
     return omega[:found.value].copy(), iters.value
+
+
+def cronos_natural_frequencies_noalloc(sim: Sim, n_modes: int = 2, max_iter: int = 200_000, tol: float = 1e-9,
+                                       seed: int = 1) -> tuple:
+    """cronos_natural_frequencies on the library's fixed device workspace (no device
+    allocation); returns (omega[:n_found], iterations)."""
+    omega = np.zeros(n_modes)
+    found, iters = _i32(0), _i32(0)
+    _check(_lib.cronos_natural_frequencies_noalloc(sim.handle, n_modes, max_iter, tol, seed, _ptr(omega),
+                                                   C.byref(found), C.byref(iters)))
+    return omega[:found.value].copy(), iters.value
+
+
+def cronos_stream_bandwidth(bytes_: int = 2 << 30, reps: int = 5, device: int = 0) -> tuple:
+    """(copy GB/s, read GB/s) of the library's plain streaming kernels over `bytes_`."""
+    c, r = _f64(0.0), _f64(0.0)
+    _check(_lib.cronos_stream_bandwidth(device, int(bytes_), int(reps), C.byref(c), C.byref(r)))
+    return c.value, r.value
 
 
 def cronos_tridiag_smallest(a, b, count: int) -> tuple:

@@ -70,6 +70,14 @@ struct DeviceArrays {
     double* chunk_part = nullptr;        // [n_chunks][kDiagFields]
     double* body_out = nullptr;          // [nb][kDiagFields]
     float* fout = nullptr;               // [n][3] force output
+    // structured-box form (see step_grid_kernel): blocks are aligned 8 x 8 x 8 cubes of a full box
+    int32_t grid = 0;
+    int32_t grid_dim[3] = {0, 0, 0};
+    int32_t* grid_halo = nullptr;        // [nblk][488] new index of each halo cell of the block's tile, -1 outside
+    int4* grid_org = nullptr;            // [nblk] grid coordinates of the block's first node
+    float* grid_k = nullptr;             // [27][26] k per (boundary class, direction)
+    float grid_kin[3] = {};              // interior k per direction kind (1, 2, 3 non-zero offsets)
+    float grid_l0[3] = {};               // rest length per direction kind
 };
 
 constexpr int kDiagFields = 20;  // ke, pe_s, pe_g, pe_c, p3, mx3, mass, min3, max3, nonfinite
@@ -121,9 +129,24 @@ struct AdjNext {
     float* vb0 = nullptr;
     float* xbl = nullptr;
 };
+// Where the adjoint gather sums the actuated springs' rest-length sensitivities.  With
+// red_groups > 0, each workgroup sums its step's sensitivities per actuation group it touches
+// (lgrp: an entry's group index within its workgroup; blk_red[b] = (count, first slot)) in LDS
+// and adds them to acc[slot]; otherwise every entry accumulates its own in sens[entry].
+struct AdjSens {
+    double2* sens = nullptr;          // [entries]
+    const uint8_t* lgrp = nullptr;    // [entries]
+    const int2* blk_red = nullptr;    // [nblk]
+    double2* acc = nullptr;           // [slots]
+    int red_groups = 0;               // largest count of a workgroup (0: per-entry sums)
+};
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             const AdjSens& sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
                              const StepParams& p, const AdjNext& next);
+// Per actuation group g: gsum[g] = the sum of acc over the slots slot_idx[slot_ptr[g] ..
+// slot_ptr[g + 1]) in that order.
+hipError_t launch_adj_group_sums(const double2* acc, const int32_t* slot_ptr, const int32_t* slot_idx, int n_groups,
+                                 double2* gsum, hipStream_t st);
 // Actuation factors of steps n0 .. n0 + steps - 1 in one launch, row k at out + k * stride.
 hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycles, long long n0, int steps,
                                   float* out, long long stride, hipStream_t st);
@@ -144,6 +167,12 @@ hipError_t launch_modes_init(const DeviceArrays& d, int cur, ModesBuffers& m, un
 // Lanczos step k: alpha[k], beta[k] and q_{k+1} from q_k and q_{k-1}.
 hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepParams& p, ModesBuffers& m, int k,
                                   hipStream_t st);
+// Fixed FP64 workspace of the allocation-free frequency entry point: a file-scope device
+// array of this many doubles (64 MiB) on every GPU the library runs on, held until the process
+// ends.  modes_scratch returns its address on `device` (which must be current), looked up
+// once per device.
+constexpr size_t kModesScratchDoubles = size_t(8) << 20;
+hipError_t modes_scratch(int device, double** ptr);
 hipError_t launch_diagnostics(const DeviceArrays& d, int cur, const StepParams& p, hipStream_t st);
 
 }  // namespace cronos

@@ -1066,23 +1066,34 @@ adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, 
 // accumulated by exactly one lane.  With nx.x set, the mass's x_bar then feeds adj_local of
 // the step before (every input of which is the mass's own), so one launch per reversed step
 // remains; nx.w and nx.xbl must not be the w and xbl this launch reads.
-template <bool ACT, int LPM>
+// RED (actuated only): the sensitivities are summed per workgroup and actuation group (see
+// AdjSens): each thread adds its entries' terms to its own LDS column of per-group sums, then
+// each wavefront reduces whole groups (columns in thread order, then a fixed cross-lane tree)
+// and one lane adds the result to the group's slot in acc; every sum has a fixed order.
+template <bool ACT, int LPM, bool RED>
 __global__ void __launch_bounds__(1024)
 adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, const float* __restrict__ xbl,
                   float* __restrict__ xb0, const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
                   const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
                   const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
                   const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
-                  double2* __restrict__ sens, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
-                  int block, int lds_slots, int stage_factors, StepParams p, AdjNext nx) {
+                  AdjSens sa, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
+                  int block, int lds_slots, int stage_factors, int fac_slots, StepParams p, AdjNext nx) {
     extern __shared__ float4 sx[];
     float4* sw = sx + lds_slots;
     float* sfac = reinterpret_cast<float*>(sw + lds_slots);   // the factor table, when staged
+    double2* red = reinterpret_cast<double2*>(sfac + fac_slots);   // RED: [count][blockDim.x]
+    double2* __restrict__ sens = sa.sens;
     const int b = logical_block(nblk);
     if (b >= nblk) return;
     const int base = b * block;
     const int t = threadIdx.x, nt = (int)blockDim.x;
     const int m = t / LPM, sub = t % LPM;
+    int2 br = make_int2(0, 0);
+    if (RED) {
+        br = sa.blk_red[b];
+        for (int g = 0; g < br.x; ++g) red[g * nt + t] = make_double2(0.0, 0.0);   // this thread's column
+    }
     const float* fac = factor;
     if (ACT && stage_factors) {   // small tables: one LDS copy per workgroup, no dependent global load
         for (int q = t; q <= n_factor; q += nt) sfac[q] = factor[q];
@@ -1116,7 +1127,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     float ax = 0.f, ay = 0.f, az = 0.f;
     // one incidence: the spring's tangent stiffness applied to w_j - w_i, and (actuated) the
     // sensitivity of the loss to its rest length, accumulated in FP64
-    auto one = [&](int e, int slot, float2 c, int g, float f, double2 acc) {
+    auto one = [&](int e, int slot, float2 c, int g, float f, double2 acc, int lg) {
         const float l0 = ACT ? c.y * f : c.y;
         const float4 xj = sx[slot];
         const float4 wj = sw[slot];
@@ -1135,9 +1146,15 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
             az += k * (nz * ndw + tr * (dwz - nz * ndw));
             if (ACT && g < n_factor) {
                 const double q = 0.5 * (double)c.y * (double)k * (double)ndw;
-                acc.x += cos_t * q;
-                acc.y += sin_t * q;
-                sens[e] = acc;
+                if (RED) {
+                    double2& r = red[lg * nt + t];
+                    r.x += cos_t * q;
+                    r.y += sin_t * q;
+                } else {
+                    acc.x += cos_t * q;
+                    acc.y += sin_t * q;
+                    sens[e] = acc;
+                }
             }
         }
     };
@@ -1151,7 +1168,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
         const int rows = (wdt - sub + LPM - 1) / LPM;
         int k = 0;
         for (; k + B <= rows; k += B) {
-            int slot[B], g[B];
+            int slot[B], g[B], lg[B];
             float2 c[B];
             float f[B];
             double2 acc[B];
@@ -1161,17 +1178,43 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
                 slot[u] = nbr[e];
                 c[u] = kl[e];
                 g[u] = ACT ? (int)grp[e] : n_factor;
-                if (ACT) acc[u] = sens[e];
+                lg[u] = RED ? (int)sa.lgrp[e] : 0;
+                if (ACT && !RED) acc[u] = sens[e];
+                else acc[u] = make_double2(0.0, 0.0);
             }
 #pragma unroll
             for (int u = 0; u < B; ++u) f[u] = ACT ? fac[g[u]] : 1.0f;
 #pragma unroll
-            for (int u = 0; u < B; ++u) one(e0 + ((k + u) * LPM + sub) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
+            for (int u = 0; u < B; ++u)
+                one(e0 + ((k + u) * LPM + sub) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u], lg[u]);
         }
         for (; k < rows; ++k) {
             const int e = e0 + (k * LPM + sub) * 64 + lane;
             const int g = ACT ? (int)grp[e] : n_factor;
-            one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
+            one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT && !RED ? sens[e] : make_double2(0.0, 0.0),
+                RED ? (int)sa.lgrp[e] : 0);
+        }
+    }
+    if (RED) {
+        __syncthreads();
+        const int wv = t >> 6, ln = t & 63, nw = nt >> 6;
+        for (int g = wv; g < br.x; g += nw) {
+            double sx_ = 0.0, sy_ = 0.0;
+            for (int q = ln; q < nt; q += 64) {
+                const double2 r = red[g * nt + q];
+                sx_ += r.x;
+                sy_ += r.y;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                sx_ += __shfl_xor(sx_, o, 64);
+                sy_ += __shfl_xor(sy_, o, 64);
+            }
+            if (ln == 0) {
+                double2 a = sa.acc[br.y + g];
+                a.x += sx_;
+                a.y += sy_;
+                sa.acc[br.y + g] = a;
+            }
         }
     }
 #pragma unroll
@@ -1187,6 +1230,130 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     xb0[3 * i + 1] = by;
     xb0[3 * i + 2] = bz;
     if (nx.x) adj_local_one(i, nx.x, nx.vstar, bx, by, bz, nx.vb1, nx.w, nx.vb0, nx.xbl, p);
+}
+
+// ---------------------------------------------------------------------------------------
+// Structured-box form (the lattice of section "Generating a Lattice" filled out to a full
+// box): every node of an nx x ny x nz grid is a mass, every pair of grid neighbours (the 26
+// directions) is a spring, the rest length depends only on the kind of direction (edge, face
+// diagonal, body diagonal), and the stiffness on the direction and on which faces of the box
+// the mass lies on (27 boundary classes; interior masses: on the kind only).  The
+// host detects this structure (cronos_create) and then no incidence data is read at all: a
+// workgroup owns one aligned 8 x 8 x 8 cube of the Morton order (512 masses, 512 threads),
+// stages it with a one-node halo as a 10 x 10 x 10 tile in LDS, and each lane visits its 26
+// tile neighbours at fixed offsets.  Directions are summed in a fixed order (dz, dy, dx
+// ascending), so the result is bitwise reproducible; it equals the other forms' CSR-order
+// sum to rounding.  Halo cells outside the box hold a far-away position whose spring has
+// k = 0, contributing exactly nothing.
+constexpr int kGridEdge = 8, kGridPitch = 10, kGridCells = 1000, kGridHalo = 488, kGridThreads = 512;
+
+struct GridArgs {
+    const float4* __restrict__ xin;
+    const float* __restrict__ vin;
+    float4* __restrict__ xout;
+    float* __restrict__ vout;
+    float* __restrict__ vstar_out;
+    const float* __restrict__ fext;
+    const int32_t* __restrict__ halo;   // [nblk][kGridHalo] new index of each halo cell, -1 outside
+    const int4* __restrict__ org;       // [nblk] grid coordinates of the block's first node
+    const float* __restrict__ kcls;     // [27][26] k per (boundary class, direction)
+    int nblk, nx, ny, nz;
+    // per direction kind (edge, face diagonal, body diagonal: 1, 2 or 3 non-zero offsets)
+    float kin[3];                       // k of interior masses (class 13)
+    float l0[3];                        // rest length
+    double q[3];                        // its square, exact in FP64
+};
+
+// Tile cell of halo slot h: the z = 0 face, the z = 9 face, then for z = 1..8 the y = 0 row,
+// the y = 9 row and the x = 0 / x = 9 ends of rows y = 1..8 (100 + 100 + 8 x 36 = 488).
+__device__ __forceinline__ int grid_halo_cell(int h) {
+    int x, y, z;
+    if (h < 200) {
+        z = h < 100 ? 0 : 9;
+        const int r = h < 100 ? h : h - 100;
+        y = r / 10;
+        x = r - 10 * y;
+    } else {
+        const int r = h - 200;
+        z = 1 + r / 36;
+        const int s = r - 36 * (z - 1);
+        if (s < 20) {
+            y = s < 10 ? 0 : 9;
+            x = s < 10 ? s : s - 10;
+        } else {
+            y = 1 + ((s - 20) >> 1);
+            x = ((s - 20) & 1) * 9;
+        }
+    }
+    return (z * kGridPitch + y) * kGridPitch + x;
+}
+
+// Sum of the 26 spring forces of the lane's mass at tile cell `cell`.  INTERIOR: every mass of
+// the wavefront is interior, so each direction's k is the same for all lanes.
+template <int EX, bool INTERIOR>
+__device__ __forceinline__ void gather_grid(const float4* __restrict__ tile, const float* __restrict__ kc, int cell,
+                                            float4 xi, const GridArgs& a, float& fx, float& fy, float& fz) {
+    fx = fy = fz = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 26; ++d) {
+        const int e = d < 13 ? d : d + 1;                 // skip the centre of the 3 x 3 x 3 stencil
+        const int ox = e % 3 - 1, oy = (e / 3) % 3 - 1, oz = e / 9 - 1;
+        const int kind = (ox != 0) + (oy != 0) + (oz != 0) - 1;
+        const float4 xj = tile[cell + (oz * kGridPitch + oy) * kGridPitch + ox];
+        const float k = INTERIOR ? a.kin[kind] : kc[d];
+        float dx, dy, dz;
+        const float fac = hooke_fac<EX>(xi.x, xi.y, xi.z, xj.x, xj.y, xj.z, k, a.l0[kind], a.q[kind], dx, dy, dz);
+        fx = __builtin_fmaf(fac, dx, fx);
+        fy = __builtin_fmaf(fac, dy, fy);
+        fz = __builtin_fmaf(fac, dz, fz);
+    }
+}
+
+template <bool EXACT>
+__global__ void __launch_bounds__(kGridThreads) step_grid_kernel(GridArgs a, StepParams p) {
+    __shared__ float4 tile[kGridCells];
+    __shared__ float kcls[27 * 26];
+    const int b = logical_block(a.nblk);
+    if (b >= a.nblk) return;
+    const int t = threadIdx.x;
+    const int i = b * kGridThreads + t;
+    // Morton-local index t: x from bits 0, 3, 6; y from 1, 4, 7; z from 2, 5, 8
+    const int lx = (t & 1) | ((t >> 2) & 2) | ((t >> 4) & 4);
+    const int ly = ((t >> 1) & 1) | ((t >> 3) & 2) | ((t >> 5) & 4);
+    const int lz = ((t >> 2) & 1) | ((t >> 4) & 2) | ((t >> 6) & 4);
+    const int cell = ((lz + 1) * kGridPitch + (ly + 1)) * kGridPitch + (lx + 1);
+    const float4 xi = a.xin[i];
+    tile[cell] = xi;
+    for (int h = t; h < kGridHalo; h += kGridThreads) {
+        const int g = a.halo[(long)b * kGridHalo + h];
+        tile[grid_halo_cell(h)] = g >= 0 ? a.xin[g] : make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+    }
+    for (int q = t; q < 27 * 26; q += kGridThreads) kcls[q] = a.kcls[q];
+    const int4 o = a.org[b];
+    const int gx = o.x + lx, gy = o.y + ly, gz = o.z + lz;
+    const int cls = (gx == 0 ? 0 : gx == a.nx - 1 ? 2 : 1) + 3 * (gy == 0 ? 0 : gy == a.ny - 1 ? 2 : 1) +
+                    9 * (gz == 0 ? 0 : gz == a.nz - 1 ? 2 : 1);
+    __syncthreads();
+    const float* kc = kcls + 26 * cls;
+    const bool interior = __builtin_amdgcn_ballot_w64(cls != 13) == 0;
+    const int mode = EXACT ? difference_mode(xi, p.safe) : kPlain;
+    float fx, fy, fz;
+    if (mode == kPlain) {
+        if (interior) gather_grid<kPlain, true>(tile, kc, cell, xi, a, fx, fy, fz);
+        else gather_grid<kPlain, false>(tile, kc, cell, xi, a, fx, fy, fz);
+    } else if (mode == kExactZ) {
+        gather_grid<kExactZ, false>(tile, kc, cell, xi, a, fx, fy, fz);
+    } else {
+        gather_grid<kExactAll, false>(tile, kc, cell, xi, a, fx, fy, fz);
+    }
+    float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
+    float4 xo;
+    integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+              a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+    a.xout[i] = xo;
+    a.vout[3 * i + 0] = vx;
+    a.vout[3 * i + 1] = vy;
+    a.vout[3 * i + 2] = vz;
 }
 
 inline int grid_for(int64_t nblk) { return (int)(((nblk + 7) / 8) * 8); }
@@ -1233,6 +1400,20 @@ bool fused_actuation(const DeviceArrays& d) { return d.grp != nullptr && (d.sp_r
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
                           float* vstar, const StepParams& p, hipStream_t st, const float* factor, int fuse,
                           int cur) {
+    if (d.grid) {
+        if (fuse) return hipErrorInvalidValue;
+        GridArgs g{xin, vin, xout, vout, vstar, d.fext, d.grid_halo, d.grid_org, d.grid_k, (int)d.nblk,
+                   d.grid_dim[0], d.grid_dim[1], d.grid_dim[2], {}, {}, {}};
+        for (int q = 0; q < 3; ++q) {
+            g.kin[q] = d.grid_kin[q];
+            g.l0[q] = d.grid_l0[q];
+            g.q[q] = (double)d.grid_l0[q] * (double)d.grid_l0[q];
+        }
+        const dim3 grid((unsigned)grid_for(d.nblk)), th(kGridThreads);
+        if (p.exact) hipLaunchKernelGGL(step_grid_kernel<true>, grid, th, 0, st, g, p);
+        else hipLaunchKernelGGL(step_grid_kernel<false>, grid, th, 0, st, g, p);
+        return hipGetLastError();
+    }
     const int mode = d.sp_rec ? kSplit : d.narrow ? kNarrow : d.packed ? kTable : kExplicit;
     if (fuse && !fused_actuation(d)) return hipErrorInvalidValue;
     StepArgs a{xin, vin, xout, vout, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
@@ -1386,28 +1567,62 @@ hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycl
 }
 
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             const AdjSens& sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
                              const StepParams& p, const AdjNext& next) {
     if (!factor) factor = d.factor;
-    // the factor table goes to LDS when small (kAdjStagedFactors entries at most)
+    // the factor table goes to LDS when small (kAdjStagedFactors entries at most); the per-group
+    // sums (RED) follow it at a 16-byte boundary
     const int stage = d.grp && d.n_factor + 1 <= kAdjStagedFactors ? 1 : 0;
-    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (stage ? (size_t)(d.n_factor + 1) * sizeof(float) : 0);
+    const int fac_slots = stage ? (d.n_factor + 1 + 3) / 4 * 4 : 0;
     const int lanes = d.lanes == 2 || d.lanes == 4 ? d.lanes : 1;
-    const dim3 g(grid_for(d.nblk)), th((unsigned)(d.block * lanes));
+    const int nt = d.block * lanes;
+    const bool red = d.grp && sens.red_groups > 0;
+    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (size_t)fac_slots * sizeof(float) +
+                       (red ? (size_t)sens.red_groups * nt * sizeof(double2) : 0);
+    const dim3 g(grid_for(d.nblk)), th((unsigned)nt);
     auto go = [&](auto k) {
         hipLaunchKernelGGL(k, g, th, lds, st, x, w, xbl, xb0, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
                            d.lane_mass, factor, sens, d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice,
-                           d.block, d.lds_slots, stage, p, next);
+                           d.block, d.lds_slots, stage, fac_slots, p, next);
     };
-    if (d.grp) {
-        if (lanes == 4) go(adj_gather_kernel<true, 4>);
-        else if (lanes == 2) go(adj_gather_kernel<true, 2>);
-        else go(adj_gather_kernel<true, 1>);
+    if (d.grp && red) {
+        if (lanes == 4) go(adj_gather_kernel<true, 4, true>);
+        else if (lanes == 2) go(adj_gather_kernel<true, 2, true>);
+        else go(adj_gather_kernel<true, 1, true>);
+    } else if (d.grp) {
+        if (lanes == 4) go(adj_gather_kernel<true, 4, false>);
+        else if (lanes == 2) go(adj_gather_kernel<true, 2, false>);
+        else go(adj_gather_kernel<true, 1, false>);
     } else {
-        if (lanes == 4) go(adj_gather_kernel<false, 4>);
-        else if (lanes == 2) go(adj_gather_kernel<false, 2>);
-        else go(adj_gather_kernel<false, 1>);
+        if (lanes == 4) go(adj_gather_kernel<false, 4, false>);
+        else if (lanes == 2) go(adj_gather_kernel<false, 2, false>);
+        else go(adj_gather_kernel<false, 1, false>);
     }
+    return hipGetLastError();
+}
+
+namespace {
+
+__global__ void adj_group_sums_kernel(const double2* __restrict__ acc, const int32_t* __restrict__ slot_ptr,
+                                      const int32_t* __restrict__ slot_idx, int n_groups, double2* __restrict__ gsum) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = slot_ptr[g]; q < slot_ptr[g + 1]; ++q) {
+        const double2 a = acc[slot_idx[q]];
+        s.x += a.x;
+        s.y += a.y;
+    }
+    gsum[g] = s;
+}
+
+}  // namespace
+
+hipError_t launch_adj_group_sums(const double2* acc, const int32_t* slot_ptr, const int32_t* slot_idx, int n_groups,
+                                 double2* gsum, hipStream_t st) {
+    if (n_groups < 1) return hipSuccess;
+    hipLaunchKernelGGL(adj_group_sums_kernel, dim3((n_groups + 255) / 256), dim3(256), 0, st, acc, slot_ptr, slot_idx,
+                       n_groups, gsum);
     return hipGetLastError();
 }
 

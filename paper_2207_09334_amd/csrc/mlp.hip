@@ -1,13 +1,28 @@
 // Surrogate network on gfx950: a 4-layer perceptron (3 exact-erf GELU hidden layers, linear
 // output) whose products run on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) with FP32
-// accumulation; weights are kept as an FP32 master copy and a BF16 shadow; Adam in FP32.
+// accumulation; weights are kept as an FP32 master copy and two BF16 shadows; Adam in FP32.
 //
-// GEMM: C[M x N] = sum_k A(m, k) B(k, n) with strided A and B (so the forward product, the
-// back-propagation through W^T and the weight gradient X^T dZ are one kernel).  A workgroup
-// (4 wavefronts) computes a 64 x 64 tile, each wavefront a 32 x 32 quarter as 2 x 2 MFMA tiles
-// of 16 x 16, stepping K by 32 through LDS.  Operand layouts of the 16x16x32 BF16 MFMA: lane l
-// supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7, and receives
-// C[4 (l / 16) + r][l % 16], r = 0..3.
+// Every product is C[M x N] = A B^T with both operands stored K-contiguous (A: M rows of K,
+// B: N rows of K), so each operand tile arrives with 16-byte vector loads along K.  To keep it
+// that way the network stores, beside each row-major activation it produces, its transpose
+// (written by the producing product's epilogue), and keeps both W and W^T as BF16 shadows:
+//   forward      Z_l = H_{l-1} W_l        A = H_{l-1} (rows x in),   B = W_l^T (out x in)
+//   input grad   dH  = dZ_l W_l^T         A = dZ_l (rows x out),     B = W_l   (in x out)
+//   weight grad  [dW_l; db_l] = [H^T; 1] dZ_l   A = [H_{l-1}^T; ones] (in+1 x rows),
+//                                               B = dZ_l^T (out x rows)
+// The row of ones appended to each transposed input makes the bias gradient (a column sum
+// of dZ) the last row of the weight-gradient product, which lands exactly where the bias
+// follows the weight in the parameter vector.  Widths are padded to multiples of 32 with zero
+// weights, so padded activations are exactly zero.
+//
+// Tiling: a workgroup of 4 wavefronts computes a 64 x 64 tile of C, each wavefront a 32 x 32
+// quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 64 (or 32) through two LDS buffers:
+// the next K-step's operands are loaded into registers while the matrix cores work on the
+// current one, then stored to the other buffer (one barrier per K-step).  The weight
+// gradients (K = the minibatch rows) split K into chunks of 512 rows computed by separate
+// workgroups into FP32 partials that one more kernel sums in a fixed order.  Operand layouts
+// of the 16x16x32 BF16 MFMA: lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j]
+// [l % 16], j = 0..7, and receives C[4 (l / 16) + r][l % 16], r = 0..3.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,20 +38,29 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64, kK = 32, kPad = 8;
+constexpr int kBM = 64, kBN = 64;   // workgroup tile
+constexpr int kWidthPad = 32;       // widths are padded to multiples of this (the MFMA's K)
+constexpr int kSplitRows = 512;     // K chunk of the weight-gradient products
 
-enum Epilogue { kFwdGelu = 0, kLinear = 1, kBwdGelu = 2, kPlain = 3 };
+enum Epilogue { kFwdGelu = 0, kLinear = 1, kBwdGelu = 2, kPartial = 3 };
 
 struct GemmArgs {
     const bf16* A;
-    long sam, sak;        // A(m, k) = A[m * sam + k * sak]
+    long lda;             // A(m, k) = A[m * lda + k], m < M
     const bf16* B;
-    long sbk, sbn;        // B(k, n) = B[k * sbk + n * sbn]
-    int M, N, K;
-    const float* bias;    // [N] (forward epilogues)
-    float* Cf;            // FP32 output, row-major M x N
-    bf16* Cb;             // BF16 output, row-major M x N
-    const float* Z;       // pre-activation, row-major M x N (backward GELU)
+    long ldb;             // B(n, k) = B[n * ldb + k], n < N
+    int M, N, K;          // K: a multiple of the K-step; lda, ldb: multiples of 8
+    int k_chunk;          // K range of workgroup z: [z k_chunk, (z + 1) k_chunk)
+    int n_real;           // columns below n_real get the bias, the transposed and FP32 outputs
+    const float* bias;    // [n_real] (forward epilogues)
+    float* Cf;            // FP32 output: Cf[m * ldcf + n] (+ z * part_stride for partials)
+    long ldcf, part_stride;
+    bf16* Cb;             // BF16 row-major output: Cb[m * ldcb + n], n < N
+    long ldcb;
+    bf16* Ct;             // BF16 transposed output: Ct[n * ldct + m], n < n_real
+    long ldct;
+    const float* Z;       // pre-activation Z[m * ldz + n] (backward GELU)
+    long ldz;
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -45,77 +69,143 @@ __device__ __forceinline__ float gelu_grad(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-template <int EPI>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) bf16 As[kTile][kK + kPad];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[kTile][kK + kPad];   // [n][k]
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x4 acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = t >> 2, lk = (t & 3) * 8;   // this thread's row and k-offset in the LDS tiles
-    for (int kb = 0; kb < g.K; kb += kK) {
-        {
-            const int m = m0 + lr;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = kb + lk + j;
-                As[lr][lk + j] = (m < g.M && k < g.K) ? g.A[(long)m * g.sam + (long)k * g.sak] : (bf16)0.0f;
-            }
-            const int n = n0 + lr;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = kb + lk + j;
-                Bs[lr][lk + j] = (n < g.N && k < g.K) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (bf16)0.0f;
-            }
-        }
-        __syncthreads();
-        const int r16 = lane & 15, k8 = (lane >> 4) * 8;
-        bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + r16][k8]);
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + r16][k8]);
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
-    }
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-                const int n = n0 + wn + j * 16 + (lane & 15);
-                if (m >= g.M || n >= g.N) continue;
-                const float v = acc[i][j][r];
-                const long o = (long)m * g.N + n;
-                if (EPI == kFwdGelu) {
-                    const float z = v + g.bias[n];
-                    g.Cf[o] = z;
-                    g.Cb[o] = (bf16)gelu(z);
-                } else if (EPI == kLinear) {
-                    g.Cf[o] = v + g.bias[n];
-                } else if (EPI == kBwdGelu) {
-                    g.Cb[o] = (bf16)(v * gelu_grad(g.Z[o]));
-                } else {
-                    g.Cf[o] = v;
-                }
-            }
+__device__ __forceinline__ uint32_t pack2(bf16 lo, bf16 hi) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
 }
 
-// dY = 2 (Y - T) / (rows * n_out) as BF16 (zero on padding rows) and per-block loss partials.
-__global__ void __launch_bounds__(256) loss_kernel(const float* Y, const float* T, bf16* dY, double* part, int rows,
-                                                   int padded_rows, int n_out) {
+template <int EPI, int BK>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    constexpr int LDK = BK + 8;               // LDS row pitch in elements (16-byte reads stay conflict-free)
+    constexpr int CPR = BK / 8;               // 16-byte chunks per tile row
+    constexpr int LOADS = kBM * CPR / 256;    // 16-byte loads per thread per operand per K-step
+    __shared__ __attribute__((aligned(16))) bf16 As[2][kBM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][kBN * LDK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int kbeg = blockIdx.z * g.k_chunk;
+    const int kend = min(g.K, kbeg + g.k_chunk);
+    const int nk = (kend - kbeg) / BK;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+    uint4 ra[LOADS], rb[LOADS];
+    auto gload = [&](int kb) {
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) {
+            const int c = t + 256 * i, row = c / CPR, kc = (c % CPR) * 8;
+            const int m = m0 + row, n = n0 + row;
+            ra[i] = m < g.M ? *reinterpret_cast<const uint4*>(g.A + (long)m * g.lda + kb + kc) : uint4{0u, 0u, 0u, 0u};
+            rb[i] = n < g.N ? *reinterpret_cast<const uint4*>(g.B + (long)n * g.ldb + kb + kc) : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) {
+            const int c = t + 256 * i, row = c / CPR, kc = (c % CPR) * 8;
+            *reinterpret_cast<uint4*>(&As[buf][row * LDK + kc]) = ra[i];
+            *reinterpret_cast<uint4*>(&Bs[buf][row * LDK + kc]) = rb[i];
+        }
+    };
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+
+    if (nk > 0) {
+        gload(kbeg);
+        sstore(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+        const int cur = it & 1;
+        if (it + 1 < nk) gload(kbeg + (it + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 32) {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wm + i * 16 + r16) * LDK + ks + k8]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wn + j * 16 + r16) * LDK + ks + k8]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (it + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = m0 + wm + i * 16 + (lane >> 4) * 4;   // rows mb .. mb + 3
+            const int n = n0 + wn + j * 16 + (lane & 15);
+            if (n >= g.N) continue;
+            if (EPI == kPartial) {
+                if (n >= g.n_real) continue;
+                float* out = g.Cf + blockIdx.z * g.part_stride;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (mb + r < g.M) out[(long)(mb + r) * g.ldcf + n] = acc[i][j][r];
+            } else if (EPI == kLinear) {
+                if (n >= g.n_real) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (mb + r < g.M) g.Cf[(long)(mb + r) * g.ldcf + n] = acc[i][j][r] + g.bias[n];
+            } else {
+                // forward / backward GELU: M is a multiple of 64 (padded minibatch rows)
+                bf16 hv[4];
+                const float bn = (EPI == kFwdGelu && n < g.n_real) ? g.bias[n] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long o = (long)(mb + r) * g.ldcb + n;
+                    if (EPI == kFwdGelu) {
+                        const float z = acc[i][j][r] + bn;
+                        g.Cf[(long)(mb + r) * g.ldcf + n] = z;
+                        hv[r] = (bf16)gelu(z);
+                    } else {
+                        hv[r] = (bf16)(acc[i][j][r] * gelu_grad(g.Z[(long)(mb + r) * g.ldz + n]));
+                    }
+                    g.Cb[o] = hv[r];
+                }
+                if (n < g.n_real)
+                    *reinterpret_cast<uint2*>(g.Ct + (long)n * g.ldct + mb) = uint2{pack2(hv[0], hv[1]), pack2(hv[2], hv[3])};
+            }
+        }
+}
+
+// Sum of `splits` FP32 partials in split order: out[i] = part[0][i] + part[1][i] + ...
+__global__ void splitk_sum_kernel(const float* part, long stride, int splits, float* out, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = part[i];
+    for (int z = 1; z < splits; ++z) s += part[z * stride + i];
+    out[i] = s;
+}
+
+// dY = 2 (Y - T) / (rows * n_out) as BF16, row-major [P][ldy] (zero on padding rows and
+// columns) and transposed [n_out][ldt]; per-block loss partials.
+__global__ void __launch_bounds__(256) loss_kernel(const float* Y, const float* T, bf16* dY, long ldy, bf16* dYt, long ldt,
+                                                   double* part, int rows, int padded_rows, int n_out) {
     __shared__ double red[256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double l = 0.0;
-    if (i < padded_rows * n_out) {
-        const int r = i / n_out;
+    if (i < padded_rows * ldy) {
+        const int r = i / (int)ldy, c = i % (int)ldy;
         float d = 0.0f;
-        if (r < rows) {
-            d = Y[i] - T[i];
+        if (r < rows && c < n_out) {
+            d = Y[r * n_out + c] - T[r * n_out + c];
             l = (double)d * (double)d;
         }
-        dY[i] = (bf16)(2.0f * d / (float)(rows * n_out));
+        const bf16 v = (bf16)(2.0f * d / (float)(rows * n_out));
+        dY[i] = v;
+        if (c < n_out) dYt[(long)c * ldt + r] = v;
     }
     red[threadIdx.x] = l;
     __syncthreads();
@@ -126,18 +216,28 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* Y, const float* 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Column sums of a BF16 matrix (bias gradients), one thread per column, rows in order.
-__global__ void colsum_kernel(const bf16* D, float* out, int rows, int cols) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += (float)D[(long)r * cols + c];
-    out[c] = s;
+// Where each layer's weights sit in the parameter vector and in the two BF16 shadows.
+struct ShadowMap {
+    long off_w[4], off_b[4];
+    int K[4], N[4], Kp[4], Np[4];
+    bf16* w[4];    // [Kp][Np]: W as stored (input-gradient products)
+    bf16* wt[4];   // [Np][Kp]: W^T (forward products)
+};
+
+__device__ __forceinline__ void write_shadow(const ShadowMap& s, long i, float v) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        if (i >= s.off_w[l] && i < s.off_b[l]) {
+            const long q = i - s.off_w[l];
+            const int k = (int)(q / s.N[l]), n = (int)(q % s.N[l]);
+            s.w[l][(long)k * s.Np[l] + n] = (bf16)v;
+            s.wt[l][(long)n * s.Kp[l] + k] = (bf16)v;
+        }
 }
 
-// Adam on the FP32 master copy; refreshes the BF16 shadow of the weight entries.
-__global__ void adam_kernel(float* p, float* m, float* v, const float* grad, bf16* shadow, const int* is_weight,
-                            long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+// Adam on the FP32 master copy; refreshes the BF16 shadows of the weight entries.
+__global__ void adam_kernel(float* p, float* m, float* v, const float* grad, ShadowMap sm, long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = grad[i];
@@ -147,22 +247,33 @@ __global__ void adam_kernel(float* p, float* m, float* v, const float* grad, bf1
     v[i] = vi;
     const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     p[i] = pi;
-    if (is_weight[i]) shadow[i] = (bf16)pi;
+    write_shadow(sm, i, pi);
 }
 
-__global__ void to_bf16_kernel(const float* src, bf16* dst, long n) {
+__global__ void shadow_kernel(const float* p, ShadowMap sm, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (bf16)src[i];
+    if (i < n) write_shadow(sm, i, p[i]);
 }
 
-// Minibatch gather: X_b[r] = bf16(X[idx[r]]), T_b[r] = T[idx[r]]; zero beyond `rows`.
-__global__ void gather_kernel(const float* X, const float* T, const int* idx, bf16* Xb, float* Tb, int rows,
-                              int padded_rows, int n_in, int n_out) {
+// Minibatch rows r < padded_rows: X_b[r][c] = bf16(X[src][c]) (zero beyond n_in and beyond
+// `rows`), X_t[c][r] for c < n_in, T_b[r] = T[src]; src = idx[r], or r when idx is NULL.
+__global__ void gather_kernel(const float* X, const float* T, const int* idx, bf16* Xb, long ldx, bf16* Xt, long ldt,
+                              float* Tb, int rows, int padded_rows, int n_in, int n_out) {
     const int r = blockIdx.x;
     if (r >= padded_rows) return;
-    const long src = r < rows ? (long)idx[r] : -1;
-    for (int c = threadIdx.x; c < n_in; c += blockDim.x) Xb[(long)r * n_in + c] = src >= 0 ? (bf16)X[src * n_in + c] : (bf16)0.0f;
-    for (int c = threadIdx.x; c < n_out; c += blockDim.x) Tb[(long)r * n_out + c] = src >= 0 ? T[src * n_out + c] : 0.0f;
+    const long src = r < rows ? (idx ? (long)idx[r] : (long)r) : -1;
+    for (int c = threadIdx.x; c < ldx; c += blockDim.x) {
+        const bf16 v = (src >= 0 && c < n_in) ? (bf16)X[src * n_in + c] : (bf16)0.0f;
+        Xb[(long)r * ldx + c] = v;
+        if (c < n_in) Xt[(long)c * ldt + r] = v;
+    }
+    if (T)
+        for (int c = threadIdx.x; c < n_out; c += blockDim.x) Tb[(long)r * n_out + c] = src >= 0 ? T[src * n_out + c] : 0.0f;
+}
+
+__global__ void fill_kernel(bf16* p, long n, float v) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (bf16)v;
 }
 
 uint64_t splitmix64(uint64_t z) {
@@ -171,6 +282,8 @@ uint64_t splitmix64(uint64_t z) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
+
+int pad_width(int w) { return (w + kWidthPad - 1) / kWidthPad * kWidthPad; }
 
 }  // namespace
 
@@ -184,25 +297,33 @@ using cronos::fail;
 
 struct cronos_mlp_t {
     int sizes[5];
-    int max_rows = 0;      // padded to a multiple of 64
+    int wp[5];             // widths padded to multiples of 32
+    int max_rows = 0;      // padded to a multiple of 64; row pitch of every transposed buffer
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     long n_params = 0;
     long off_w[4], off_b[4];
     float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
-    bf16* shadow = nullptr;
-    int* is_weight = nullptr;
+    bf16 *w[4] = {}, *wt[4] = {};      // BF16 shadows [wp[l]][wp[l+1]] and [wp[l+1]][wp[l]]
+    ShadowMap smap;
     int step = 0;
-    // activations for max_rows
-    bf16* x = nullptr;                 // [rows][sizes[0]]
-    float* z[3] = {nullptr, nullptr, nullptr};
-    bf16* h[3] = {nullptr, nullptr, nullptr};
-    float* y = nullptr;
+    // activations for max_rows rows (row-major [rows][width]; transposed [width (+1)][max_rows])
+    float* xin = nullptr;              // [rows][sizes[0]] FP32 staging of uploaded inputs
+    bf16* x = nullptr;                 // [rows][wp[0]]
+    bf16* xt = nullptr;                // [sizes[0] + 1][max_rows], last row ones
+    float* z[3] = {};                  // [rows][wp[l+1]]
+    bf16* h[3] = {};
+    bf16* ht[3] = {};                  // [sizes[l+1] + 1][max_rows], last row ones
+    float* y = nullptr;                // [rows][sizes[4]]
     float* t = nullptr;
-    bf16* dy = nullptr;
-    bf16* dz[3] = {nullptr, nullptr, nullptr};
-    double* part = nullptr;
+    bf16* dy = nullptr;                // [rows][wp[4]]
+    bf16* dyt = nullptr;               // [sizes[4]][max_rows]
+    bf16* dz[3] = {};                  // [rows][wp[l+1]]
+    bf16* dzt[3] = {};                 // [sizes[l+1]][max_rows]
+    float* part_w = nullptr;           // split-K partials of the weight gradients
+    long part_stride = 0;
+    double* part = nullptr;            // loss partials
     // training data
     float* data_x = nullptr;
     float* data_t = nullptr;
@@ -213,18 +334,30 @@ struct cronos_mlp_t {
 namespace {
 
 template <int EPI>
-hipError_t gemm(hipStream_t st, const bf16* A, long sam, long sak, const bf16* B, long sbk, long sbn, int M, int N, int K,
-                const float* bias, float* Cf, bf16* Cb, const float* Z) {
-    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, bias, Cf, Cb, Z};
-    dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile);
-    hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, st, g);
+hipError_t gemm(hipStream_t st, GemmArgs g, int splits = 1) {
+    dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, splits);
+    if (splits == 1) g.k_chunk = g.K;
+    if (g.K % 64 == 0 && g.k_chunk % 64 == 0)
+        hipLaunchKernelGGL((gemm_kernel<EPI, 64>), grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<EPI, 32>), grid, dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
 void free_mlp(cronos_mlp_t* q) {
-    void* ptrs[] = {q->p, q->m, q->v, q->grad, q->shadow, q->is_weight, q->x, q->z[0], q->z[1], q->z[2], q->h[0],
-                    q->h[1], q->h[2], q->y, q->t, q->dy, q->dz[0], q->dz[1], q->dz[2], q->part, q->data_x, q->data_t,
-                    q->idx};
+    std::vector<void*> ptrs = {q->p, q->m, q->v, q->grad, q->xin, q->x, q->xt, q->y, q->t, q->dy, q->dyt, q->part_w,
+                               q->part, q->data_x, q->data_t, q->idx};
+    for (int l = 0; l < 4; ++l) {
+        ptrs.push_back(q->w[l]);
+        ptrs.push_back(q->wt[l]);
+    }
+    for (int l = 0; l < 3; ++l) {
+        ptrs.push_back(q->z[l]);
+        ptrs.push_back(q->h[l]);
+        ptrs.push_back(q->ht[l]);
+        ptrs.push_back(q->dz[l]);
+        ptrs.push_back(q->dzt[l]);
+    }
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (q->own_stream && q->stream) (void)hipStreamDestroy(q->stream);
@@ -233,73 +366,136 @@ void free_mlp(cronos_mlp_t* q) {
 // Forward over `rows` (<= max_rows, padded to 64) rows already in q->x.
 cronos_status forward_dev(cronos_mlp_t* q, int rows) {
     const int P = (rows + 63) / 64 * 64;
+    const long R = q->max_rows;
     const bf16* in = q->x;
     for (int l = 0; l < 3; ++l) {
-        const int K = q->sizes[l], N = q->sizes[l + 1];
-        HIP_TRY(gemm<kFwdGelu>(q->stream, in, K, 1, q->shadow + q->off_w[l], N, 1, P, N, K, q->p + q->off_b[l], q->z[l],
-                               q->h[l], nullptr));
+        GemmArgs g{};
+        g.A = in;
+        g.lda = q->wp[l];
+        g.B = q->wt[l];
+        g.ldb = q->wp[l];
+        g.M = P;
+        g.N = q->wp[l + 1];
+        g.K = q->wp[l];
+        g.n_real = q->sizes[l + 1];
+        g.bias = q->p + q->off_b[l];
+        g.Cf = q->z[l];
+        g.ldcf = q->wp[l + 1];
+        g.Cb = q->h[l];
+        g.ldcb = q->wp[l + 1];
+        g.Ct = q->ht[l];
+        g.ldct = R;
+        HIP_TRY(gemm<kFwdGelu>(q->stream, g));
         in = q->h[l];
     }
-    const int K = q->sizes[3], N = q->sizes[4];
-    HIP_TRY(gemm<kLinear>(q->stream, in, K, 1, q->shadow + q->off_w[3], N, 1, P, N, K, q->p + q->off_b[3], q->y, nullptr,
-                          nullptr));
+    GemmArgs g{};
+    g.A = in;
+    g.lda = q->wp[3];
+    g.B = q->wt[3];
+    g.ldb = q->wp[3];
+    g.M = P;
+    g.N = q->wp[4];
+    g.K = q->wp[3];
+    g.n_real = q->sizes[4];
+    g.bias = q->p + q->off_b[3];
+    g.Cf = q->y;
+    g.ldcf = q->sizes[4];
+    HIP_TRY(gemm<kLinear>(q->stream, g));
     return CRONOS_OK;
 }
 
-// Loss and gradients for `rows` rows whose inputs are in q->x and targets in q->t.
+// Loss and gradients for `rows` rows whose inputs are in q->x / q->xt and targets in q->t.
 cronos_status backward_dev(cronos_mlp_t* q, int rows) {
     const int P = (rows + 63) / 64 * 64;
+    const long R = q->max_rows;
     const int n_out = q->sizes[4];
-    const int nel = P * n_out;
-    hipLaunchKernelGGL(loss_kernel, dim3((nel + 255) / 256), dim3(256), 0, q->stream, q->y, q->t, q->dy, q->part, rows, P,
-                       n_out);
+    const int nel = P * q->wp[4];
+    hipLaunchKernelGGL(loss_kernel, dim3((nel + 255) / 256), dim3(256), 0, q->stream, q->y, q->t, q->dy, (long)q->wp[4],
+                       q->dyt, R, q->part, rows, P, n_out);
     HIP_TRY(hipGetLastError());
-    const bf16* dnext = q->dy;
+    const int splits = (P + kSplitRows - 1) / kSplitRows;
+    const bf16* dnext = q->dy;     // [P][wp[l+1]]
+    const bf16* dnext_t = q->dyt;  // [sizes[l+1]][R]
     for (int l = 3; l >= 0; --l) {
         const int K = q->sizes[l], N = q->sizes[l + 1];
-        const bf16* hin = l ? q->h[l - 1] : q->x;
-        // dW_l = H_in^T dZ_l : (K x P) (P x N)
-        HIP_TRY(gemm<kPlain>(q->stream, hin, 1, K, dnext, N, 1, K, N, P, nullptr, q->grad + q->off_w[l], nullptr, nullptr));
-        hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, q->stream, dnext, q->grad + q->off_b[l], P, N);
-        HIP_TRY(hipGetLastError());
+        // [dW_l; db_l] = [H_in^T; 1] dZ_l : (K + 1) x N, summed over the P rows
+        GemmArgs g{};
+        g.A = l ? q->ht[l - 1] : q->xt;
+        g.lda = R;
+        g.B = dnext_t;
+        g.ldb = R;
+        g.M = K + 1;
+        g.N = N;
+        g.K = P;
+        g.k_chunk = kSplitRows;
+        g.n_real = N;
+        g.ldcf = N;
+        if (splits == 1) {
+            g.Cf = q->grad + q->off_w[l];
+            HIP_TRY(gemm<kPartial>(q->stream, g, 1));
+        } else {
+            g.Cf = q->part_w;
+            g.part_stride = q->part_stride;
+            HIP_TRY(gemm<kPartial>(q->stream, g, splits));
+            const long n = (long)(K + 1) * N;
+            hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q->stream, q->part_w,
+                               q->part_stride, splits, q->grad + q->off_w[l], n);
+            HIP_TRY(hipGetLastError());
+        }
         if (l) {
-            // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1}) : (P x N) (N x K)
-            HIP_TRY(gemm<kBwdGelu>(q->stream, dnext, N, 1, q->shadow + q->off_w[l], 1, N, P, K, N, nullptr, nullptr,
-                                   q->dz[l - 1], q->z[l - 1]));
+            // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1}) : (P x wp[l+1]) (wp[l+1] x wp[l])
+            GemmArgs d{};
+            d.A = dnext;
+            d.lda = q->wp[l + 1];
+            d.B = q->w[l];
+            d.ldb = q->wp[l + 1];
+            d.M = P;
+            d.N = q->wp[l];
+            d.K = q->wp[l + 1];
+            d.n_real = K;
+            d.Cb = q->dz[l - 1];
+            d.ldcb = q->wp[l];
+            d.Ct = q->dzt[l - 1];
+            d.ldct = R;
+            d.Z = q->z[l - 1];
+            d.ldz = q->wp[l];
+            HIP_TRY(gemm<kBwdGelu>(q->stream, d));
             dnext = q->dz[l - 1];
+            dnext_t = q->dzt[l - 1];
         }
     }
     return CRONOS_OK;
 }
 
+// Rows of the minibatch from device arrays (idx == nullptr: the first `rows` rows in order).
+cronos_status gather_rows(cronos_mlp_t* q, const float* X, const float* T, const int* idx, int rows) {
+    const int P = (rows + 63) / 64 * 64;
+    hipLaunchKernelGGL(gather_kernel, dim3(P), dim3(128), 0, q->stream, X, T, idx, q->x, (long)q->wp[0], q->xt,
+                       (long)q->max_rows, q->t, rows, P, q->sizes[0], q->sizes[4]);
+    HIP_TRY(hipGetLastError());
+    return CRONOS_OK;
+}
+
 cronos_status upload_rows(cronos_mlp_t* q, const float* x, const float* t, int rows) {
     const int n_in = q->sizes[0], n_out = q->sizes[4];
-    const int P = (rows + 63) / 64 * 64;
-    std::vector<bf16> hx((size_t)P * n_in, (bf16)0.0f);
-    for (long i = 0; i < (long)rows * n_in; ++i) hx[i] = (bf16)x[i];
-    HIP_TRY(hipMemcpyAsync(q->x, hx.data(), hx.size() * sizeof(bf16), hipMemcpyHostToDevice, q->stream));
-    if (t) {
-        std::vector<float> ht((size_t)P * n_out, 0.0f);
-        std::memcpy(ht.data(), t, (size_t)rows * n_out * sizeof(float));
-        HIP_TRY(hipMemcpyAsync(q->t, ht.data(), ht.size() * sizeof(float), hipMemcpyHostToDevice, q->stream));
-    }
-    HIP_TRY(hipStreamSynchronize(q->stream));   // host staging buffers go out of scope
-    return CRONOS_OK;
+    HIP_TRY(hipMemcpyAsync(q->xin, x, (size_t)rows * n_in * sizeof(float), hipMemcpyHostToDevice, q->stream));
+    // targets: the loss reads rows below `rows` only
+    if (t) HIP_TRY(hipMemcpyAsync(q->t, t, (size_t)rows * n_out * sizeof(float), hipMemcpyHostToDevice, q->stream));
+    return gather_rows(q, q->xin, nullptr, nullptr, rows);
 }
 
 cronos_status adam_dev(cronos_mlp_t* q, double lr, double b1, double b2, double eps) {
     q->step += 1;
     const float c1 = (float)(1.0 - std::pow(b1, q->step)), c2 = (float)(1.0 - std::pow(b2, q->step));
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((q->n_params + 255) / 256)), dim3(256), 0, q->stream, q->p, q->m,
-                       q->v, q->grad, q->shadow, q->is_weight, q->n_params, (float)lr, (float)b1, (float)b2, (float)eps,
-                       c1, c2);
+                       q->v, q->grad, q->smap, q->n_params, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
     HIP_TRY(hipGetLastError());
     return CRONOS_OK;
 }
 
 double loss_from_parts(cronos_mlp_t* q, int rows, cronos_status* st) {
     const int P = (rows + 63) / 64 * 64;
-    const int nb = (P * q->sizes[4] + 255) / 256;
+    const int nb = (P * q->wp[4] + 255) / 256;
     std::vector<double> h(nb);
     *st = CRONOS_OK;
     if (hipMemcpyAsync(h.data(), q->part, nb * sizeof(double), hipMemcpyDeviceToHost, q->stream) != hipSuccess ||
@@ -321,9 +517,13 @@ extern "C" cronos_status cronos_mlp_create(const int32_t* sizes, const double* p
     *out = nullptr;
     for (int l = 0; l < 5; ++l)
         if (sizes[l] < 1 || sizes[l] > 4096) return fail(CRONOS_EINVAL, "mlp_create: layer width out of range");
+    if (max_rows > (1 << 20)) return fail(CRONOS_EINVAL, "mlp_create: max_rows above 2^20");
     auto* q = new (std::nothrow) cronos_mlp_t;
     if (!q) return fail(CRONOS_ENOMEM, "mlp_create: out of memory");
-    for (int l = 0; l < 5; ++l) q->sizes[l] = sizes[l];
+    for (int l = 0; l < 5; ++l) {
+        q->sizes[l] = sizes[l];
+        q->wp[l] = pad_width(sizes[l]);
+    }
     q->max_rows = (max_rows + 63) / 64 * 64;
     q->device = device;
     long off = 0;
@@ -343,33 +543,64 @@ extern "C" cronos_status cronos_mlp_create(const int32_t* sizes, const double* p
             q->own_stream = true;
         }
         const long n = q->n_params, R = q->max_rows;
-        HIP_TRY(hipMalloc((void**)&q->p, n * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->m, n * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->v, n * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->grad, n * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->shadow, n * sizeof(bf16)));
-        HIP_TRY(hipMalloc((void**)&q->is_weight, n * sizeof(int)));
-        HIP_TRY(hipMalloc((void**)&q->x, R * sizes[0] * sizeof(bf16)));
-        for (int l = 0; l < 3; ++l) {
-            HIP_TRY(hipMalloc((void**)&q->z[l], R * sizes[l + 1] * sizeof(float)));
-            HIP_TRY(hipMalloc((void**)&q->h[l], R * sizes[l + 1] * sizeof(bf16)));
-            HIP_TRY(hipMalloc((void**)&q->dz[l], R * sizes[l + 1] * sizeof(bf16)));
+        auto dmalloc = [&](auto** ptr, size_t count) -> hipError_t {
+            return hipMalloc((void**)ptr, std::max<size_t>(count, 1) * sizeof(**ptr));
+        };
+        HIP_TRY(dmalloc(&q->p, n));
+        HIP_TRY(dmalloc(&q->m, n));
+        HIP_TRY(dmalloc(&q->v, n));
+        HIP_TRY(dmalloc(&q->grad, n));
+        for (int l = 0; l < 4; ++l) {
+            const size_t cnt = (size_t)q->wp[l] * q->wp[l + 1];
+            HIP_TRY(dmalloc(&q->w[l], cnt));
+            HIP_TRY(dmalloc(&q->wt[l], cnt));
+            HIP_TRY(hipMemsetAsync(q->w[l], 0, cnt * sizeof(bf16), q->stream));
+            HIP_TRY(hipMemsetAsync(q->wt[l], 0, cnt * sizeof(bf16), q->stream));
+            q->smap.off_w[l] = q->off_w[l];
+            q->smap.off_b[l] = q->off_b[l];
+            q->smap.K[l] = sizes[l];
+            q->smap.N[l] = sizes[l + 1];
+            q->smap.Kp[l] = q->wp[l];
+            q->smap.Np[l] = q->wp[l + 1];
+            q->smap.w[l] = q->w[l];
+            q->smap.wt[l] = q->wt[l];
         }
-        HIP_TRY(hipMalloc((void**)&q->y, R * sizes[4] * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->t, R * sizes[4] * sizeof(float)));
-        HIP_TRY(hipMalloc((void**)&q->dy, R * sizes[4] * sizeof(bf16)));
-        HIP_TRY(hipMalloc((void**)&q->part, ((R * sizes[4] + 255) / 256) * sizeof(double)));
+        HIP_TRY(dmalloc(&q->xin, R * sizes[0]));
+        HIP_TRY(dmalloc(&q->x, R * q->wp[0]));
+        HIP_TRY(dmalloc(&q->xt, (sizes[0] + 1) * R));
+        for (int l = 0; l < 3; ++l) {
+            HIP_TRY(dmalloc(&q->z[l], R * q->wp[l + 1]));
+            HIP_TRY(dmalloc(&q->h[l], R * q->wp[l + 1]));
+            HIP_TRY(dmalloc(&q->ht[l], (sizes[l + 1] + 1) * R));
+            HIP_TRY(dmalloc(&q->dz[l], R * q->wp[l + 1]));
+            HIP_TRY(dmalloc(&q->dzt[l], sizes[l + 1] * R));
+        }
+        HIP_TRY(dmalloc(&q->y, R * sizes[4]));
+        HIP_TRY(dmalloc(&q->t, R * sizes[4]));
+        HIP_TRY(dmalloc(&q->dy, R * q->wp[4]));
+        HIP_TRY(dmalloc(&q->dyt, sizes[4] * R));
+        HIP_TRY(dmalloc(&q->part, (R * q->wp[4] + 255) / 256));
+        // split-K partials of the largest weight gradient at max_rows rows
+        const int splits = (int)((R + kSplitRows - 1) / kSplitRows);
+        long biggest = 0;
+        for (int l = 0; l < 4; ++l) biggest = std::max<long>(biggest, (long)(sizes[l] + 1) * sizes[l + 1]);
+        q->part_stride = biggest;
+        if (splits > 1) HIP_TRY(dmalloc(&q->part_w, (size_t)splits * biggest));
+        // the appended row of ones of every transposed layer input
+        auto ones = [&](bf16* base, int row) -> hipError_t {
+            hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, q->stream, base + (long)row * R, R,
+                               1.0f);
+            return hipGetLastError();
+        };
+        HIP_TRY(ones(q->xt, sizes[0]));
+        for (int l = 0; l < 3; ++l) HIP_TRY(ones(q->ht[l], sizes[l + 1]));
         std::vector<float> hp(n), zero(n, 0.0f);
-        std::vector<int> iw(n, 0);
         for (long i = 0; i < n; ++i) hp[i] = (float)params[i];
-        for (int l = 0; l < 4; ++l)
-            for (long i = q->off_w[l]; i < q->off_b[l]; ++i) iw[i] = 1;
-        HIP_TRY(hipMemcpy(q->p, hp.data(), n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(q->m, zero.data(), n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(q->v, zero.data(), n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(q->grad, zero.data(), n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(q->is_weight, iw.data(), n * sizeof(int), hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q->stream, q->p, q->shadow, n);
+        HIP_TRY(hipMemcpyAsync(q->p, hp.data(), n * sizeof(float), hipMemcpyHostToDevice, q->stream));
+        HIP_TRY(hipMemcpyAsync(q->m, zero.data(), n * sizeof(float), hipMemcpyHostToDevice, q->stream));
+        HIP_TRY(hipMemcpyAsync(q->v, zero.data(), n * sizeof(float), hipMemcpyHostToDevice, q->stream));
+        HIP_TRY(hipMemcpyAsync(q->grad, zero.data(), n * sizeof(float), hipMemcpyHostToDevice, q->stream));
+        hipLaunchKernelGGL(shadow_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q->stream, q->p, q->smap, n);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(q->stream));
         return CRONOS_OK;
@@ -406,7 +637,6 @@ extern "C" cronos_status cronos_mlp_forward(cronos_mlp q, const float* x, int64_
     if (!q || !x || !y || rows < 0) return fail(CRONOS_EINVAL, "mlp_forward: bad arguments");
     HIP_TRY(hipSetDevice(q->device));
     const int n_out = q->sizes[4];
-    std::vector<float> hy;
     for (int64_t r0 = 0; r0 < rows; r0 += q->max_rows) {
         const int r = (int)std::min<int64_t>(q->max_rows, rows - r0);
         cronos_status st = upload_rows(q, x + r0 * q->sizes[0], nullptr, r);
@@ -465,6 +695,7 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
         q->data_x = nullptr;
         q->data_t = nullptr;
         q->idx = nullptr;
+        q->data_rows = 0;
         HIP_TRY(hipMalloc((void**)&q->data_x, (size_t)rows * n_in * sizeof(float)));
         HIP_TRY(hipMalloc((void**)&q->data_t, (size_t)rows * n_out * sizeof(float)));
         HIP_TRY(hipMalloc((void**)&q->idx, (size_t)rows * sizeof(int)));
@@ -488,11 +719,8 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
         int64_t seen = 0;
         for (int64_t b0 = 0; b0 < rows; b0 += batch) {
             const int r = (int)std::min<int64_t>(batch, rows - b0);
-            const int P = (r + 63) / 64 * 64;
-            hipLaunchKernelGGL(gather_kernel, dim3(P), dim3(128), 0, q->stream, q->data_x, q->data_t, q->idx + b0, q->x, q->t,
-                               r, P, n_in, n_out);
-            HIP_TRY(hipGetLastError());
-            cronos_status st = forward_dev(q, r);
+            cronos_status st = gather_rows(q, q->data_x, q->data_t, q->idx + b0, r);
+            if (st == CRONOS_OK) st = forward_dev(q, r);
             if (st == CRONOS_OK) st = backward_dev(q, r);
             const double lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * (double)step++ / (double)last));
             if (st == CRONOS_OK) st = adam_dev(q, lr_t, 0.9, 0.999, 1e-8);

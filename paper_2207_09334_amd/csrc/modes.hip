@@ -15,6 +15,13 @@
 // bitwise repeatable.
 #include "kernels.h"
 
+#include <mutex>
+#include <vector>
+
+// Workspace of cronos_natural_frequencies_noalloc (each GPU holds its own copy).  Host code
+// never uses this name as an address: modes_scratch looks the device address up.
+static __device__ __align__(256) double scratch[cronos::kModesScratchDoubles];
+
 namespace cronos {
 namespace {
 
@@ -289,6 +296,22 @@ hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepPara
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(modes_scale_kernel, dim3(gv), dim3(256), 0, st, m.part_u, gv, qw, m.beta, k, n);
     return hipGetLastError();
+}
+
+hipError_t modes_scratch(int device, double** ptr) {
+    static std::mutex mu;
+    static std::vector<double*> addr;   // per device ordinal
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace cronos

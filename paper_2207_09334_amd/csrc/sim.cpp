@@ -77,7 +77,17 @@ struct RolloutBuffers {
     float* xb[2] = {nullptr, nullptr};
     float* vb[2] = {nullptr, nullptr};
     float* xbl[2] = {nullptr, nullptr};   // [3N] x_bar before the spring sum, alternating as w
-    double2* sens = nullptr;  // [entries]
+    double2* sens = nullptr;  // [entries] per-entry sensitivity sums (when the per-group ones do not fit)
+    // per-(workgroup, actuation group) sensitivity sums (see cronos::AdjSens), built once
+    bool red_built = false;
+    int32_t red_groups = 0;        // largest number of groups of a workgroup; 0: per-entry sums
+    int32_t red_slots = 0;
+    uint8_t* lgrp = nullptr;       // [entries]
+    int2* blk_red = nullptr;       // [nblk] (count, first slot)
+    double2* acc = nullptr;        // [slots]
+    int32_t* slot_ptr = nullptr;   // [n_factor + 1] slots of each group, in workgroup order
+    int32_t* slot_idx = nullptr;   // [slots]
+    double2* gsum = nullptr;       // [n_factor]
     size_t cap_seg = 0, cap_ck = 0;
     // the reverse sweep captured as one HIP graph, reused while everything it bakes in (the
     // rollout's extent, the buffers, the actuation frequency) is unchanged
@@ -119,7 +129,7 @@ void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
     void* ptrs[] = {d.narrow, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
                     d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
-                    d.body_out, d.fout};
+                    d.body_out, d.fout, d.grid_halo, d.grid_org, d.grid_k};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& g : s->graph)
@@ -131,7 +141,7 @@ void free_device(cronos_sim_t* s) {
     if (r.side) (void)hipStreamDestroy(r.side);
     void* rp[] = {r.seg_f[0], r.seg_f[1], r.ck_x, r.ck_v, r.seg_x[0], r.seg_x[1], r.seg_v[0], r.seg_v[1], r.seg_vs[0],
                   r.seg_vs[1], r.lossw, r.w[0], r.w[1], r.xb[0], r.xb[1], r.vb[0], r.vb[1],
-                  r.xbl[0], r.xbl[1], r.sens};
+                  r.xbl[0], r.xbl[1], r.sens, r.lgrp, r.blk_red, r.acc, r.slot_ptr, r.slot_idx, r.gsum};
     for (void* p : rp)
         if (p) (void)hipFree(p);
     if (s->h_x) (void)hipHostFree(s->h_x);
@@ -154,6 +164,155 @@ cronos_status upload(T** dst, const T* src, size_t count) {
         cronos_status st_ = (expr);              \
         if (st_ != CRONOS_OK) return st_;        \
     } while (0)
+
+// Structured-box form (see step_grid_kernel): host arrays of a system that is a full grid of
+// masses in aligned 8 x 8 x 8 Morton blocks with all 26 neighbour springs, passive, rest
+// length fixed per direction and k fixed per (boundary class, direction).  Returns false
+// (and builds nothing) when the system is not of that shape.
+struct GridHost {
+    int32_t dim[3] = {0, 0, 0};
+    std::vector<int32_t> halo;   // [nblk][488]
+    std::vector<int4> org;       // [nblk]
+    std::vector<float> kcls;     // [27][26]
+    float kin[3] = {}, l0[3] = {};   // per direction kind: 1, 2 or 3 non-zero offsets
+};
+
+// Direction index of a neighbour offset (dx, dy, dz) in {-1, 0, 1}^3 \ 0: (dz, dy, dx)
+// lexicographic, the order of the device's sum; the opposite direction is 25 - index.
+inline int grid_direction(int dx, int dy, int dz) {
+    const int e = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+    return e < 13 ? e : e - 1;
+}
+
+bool detect_grid(const cronos_desc& d, const cronos::Layout& L, GridHost& G) {
+    constexpr int E = 8, B = E * E * E;
+    if (!d.grid || L.nb != 1 || L.block != B || d.group) return false;
+    const int64_t n = L.n, s = L.s;
+    if (n % B) return false;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], d.grid[3 * i + c]);
+            hi[c] = std::max(hi[c], d.grid[3 * i + c]);
+        }
+    int64_t cells = 1;
+    for (int c = 0; c < 3; ++c) {
+        G.dim[c] = hi[c] - lo[c] + 1;
+        if (G.dim[c] < E || G.dim[c] % E) return false;
+        cells *= G.dim[c];
+    }
+    if (cells != n) return false;
+    const int nx = G.dim[0], ny = G.dim[1], nz = G.dim[2];
+    auto cell_of = [&](int32_t o, int c) { return d.grid[3 * (int64_t)o + c] - lo[c]; };
+    // every block is an aligned cube in Morton order: local index t holds (x, y, z) from its
+    // interleaved bits
+    std::vector<int32_t> at((size_t)n, -1);   // grid cell -> new index
+    const int64_t nblk = n / B;
+    G.org.assign((size_t)nblk, make_int4(0, 0, 0, 0));
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int32_t o0 = L.perm[b * B];
+        const int x0 = cell_of(o0, 0), y0 = cell_of(o0, 1), z0 = cell_of(o0, 2);
+        if (x0 % E || y0 % E || z0 % E) return false;
+        G.org[b] = make_int4(x0, y0, z0, 0);
+        for (int t = 0; t < B; ++t) {
+            const int lx = (t & 1) | ((t >> 2) & 2) | ((t >> 4) & 4);
+            const int ly = ((t >> 1) & 1) | ((t >> 3) & 2) | ((t >> 5) & 4);
+            const int lz = ((t >> 2) & 1) | ((t >> 4) & 2) | ((t >> 6) & 4);
+            const int32_t o = L.perm[b * B + t];
+            const int x = cell_of(o, 0), y = cell_of(o, 1), z = cell_of(o, 2);
+            if (x != x0 + lx || y != y0 + ly || z != z0 + lz) return false;
+            int32_t& slot = at[((int64_t)z * ny + y) * nx + x];
+            if (slot >= 0) return false;
+            slot = (int32_t)(b * B + t);
+        }
+    }
+    // springs: exactly the pairs of grid neighbours, each once
+    int64_t expected = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                if (grid_direction(dx, dy, dz) < 13 && (dx || dy || dz))
+                    expected += (int64_t)(nx - std::abs(dx)) * (ny - std::abs(dy)) * (nz - std::abs(dz));
+    if (s != expected) return false;
+    auto cls = [&](int x, int y, int z) {
+        return (x == 0 ? 0 : x == nx - 1 ? 2 : 1) + 3 * (y == 0 ? 0 : y == ny - 1 ? 2 : 1) +
+               9 * (z == 0 ? 0 : z == nz - 1 ? 2 : 1);
+    };
+    std::vector<uint32_t> seen((size_t)n, 0u);   // per input mass: directions met
+    std::vector<float> kc(27 * 26, -1.0f);
+    float l0d[26];
+    bool l0set[26] = {};
+    auto put = [&](float& slot, float v) {
+        if (slot < 0.0f) slot = v;
+        return slot == v;
+    };
+    for (int64_t q = 0; q < s; ++q) {
+        const int32_t i = d.ends[2 * q], j = d.ends[2 * q + 1];
+        const int xi = cell_of(i, 0), yi = cell_of(i, 1), zi = cell_of(i, 2);
+        const int xj = cell_of(j, 0), yj = cell_of(j, 1), zj = cell_of(j, 2);
+        const int dx = xj - xi, dy = yj - yi, dz = zj - zi;
+        if (std::abs(dx) > 1 || std::abs(dy) > 1 || std::abs(dz) > 1 || !(dx || dy || dz)) return false;
+        const int di = grid_direction(dx, dy, dz), dj = 25 - di;
+        if ((seen[i] >> di) & 1u) return false;
+        if ((seen[j] >> dj) & 1u) return false;
+        seen[i] |= 1u << di;
+        seen[j] |= 1u << dj;
+        const float k = (float)d.k[q], l0 = (float)d.rest[q];
+        if (!put(kc[26 * cls(xi, yi, zi) + di], k) || !put(kc[26 * cls(xj, yj, zj) + dj], k)) return false;
+        for (int dd : {di, dj}) {
+            if (!l0set[dd]) {
+                l0d[dd] = l0;
+                l0set[dd] = true;
+            } else if (l0d[dd] != l0) {
+                return false;
+            }
+        }
+    }
+    for (int dd = 0; dd < 26; ++dd)
+        if (!l0set[dd]) return false;
+    for (float& k : kc)
+        if (k < 0.0f) k = 0.0f;   // a direction leaving the box: no spring
+    G.kcls = kc;
+    // rest length, and interior k, the same for every direction of a kind
+    bool kind_set[3] = {};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!(dx || dy || dz)) continue;
+                const int dd = grid_direction(dx, dy, dz), kind = (dx != 0) + (dy != 0) + (dz != 0) - 1;
+                const float kin = kc[26 * 13 + dd];
+                if (!kind_set[kind]) {
+                    kind_set[kind] = true;
+                    G.kin[kind] = kin;
+                    G.l0[kind] = l0d[dd];
+                } else if (G.kin[kind] != kin || G.l0[kind] != l0d[dd]) {
+                    return false;
+                }
+            }
+    // halo cells of every block's 10 x 10 x 10 tile, in the device's enumeration
+    G.halo.assign((size_t)nblk * 488, -1);
+    cronos::parallel_for(nblk, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            int h = 0;
+            auto add = [&](int cx, int cy, int cz) {
+                const int x = G.org[b].x + cx - 1, y = G.org[b].y + cy - 1, z = G.org[b].z + cz - 1;
+                int32_t g = -1;
+                if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) g = at[((int64_t)z * ny + y) * nx + x];
+                G.halo[(size_t)b * 488 + h++] = g;
+            };
+            for (int cz : {0, 9})
+                for (int cy = 0; cy < 10; ++cy)
+                    for (int cx = 0; cx < 10; ++cx) add(cx, cy, cz);
+            for (int cz = 1; cz <= 8; ++cz) {
+                for (int cy : {0, 9})
+                    for (int cx = 0; cx < 10; ++cx) add(cx, cy, cz);
+                for (int cy = 1; cy <= 8; ++cy)
+                    for (int cx : {0, 9}) add(cx, cy, cz);
+            }
+        }
+    }, 16);
+    return true;
+}
 
 // Largest natural frequency of the rest-state system (springs k n n^T plus the contact
 // plane's k_g on z) among free masses.  Gershgorin first; if that bound is not conclusive,
@@ -732,6 +891,11 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         for (int32_t bb = b + 1; bb <= sim->nb; ++bb) body_chunk[bb] = (int32_t)chunks.size();
     }
 
+    // ---- structured-box form
+    GridHost gridh;
+    const uint32_t no_grid = CRONOS_NO_GRID | CRONOS_NO_TABLE | CRONOS_SPLIT | CRONOS_WIDE_ENTRIES | CRONOS_RESIDENT;
+    const bool use_grid = lanes == 1 && !(d->flags & no_grid) && detect_grid(*d, L, gridh);
+
     // ---- device
     cronos::DeviceArrays& D = sim->d;
     D.n = n;
@@ -844,6 +1008,17 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
         TRY(upload<double>(&D.chunk_part, nullptr, chunks.size() * cronos::kDiagFields));
         TRY(upload<double>(&D.body_out, nullptr, (size_t)sim->nb * cronos::kDiagFields));
         TRY(upload<float>(&D.fout, nullptr, 3 * n));
+        if (use_grid) {
+            TRY(upload(&D.grid_halo, gridh.halo.data(), gridh.halo.size()));
+            TRY(upload(&D.grid_org, gridh.org.data(), gridh.org.size()));
+            TRY(upload(&D.grid_k, gridh.kcls.data(), gridh.kcls.size()));
+            for (int c = 0; c < 3; ++c) D.grid_dim[c] = gridh.dim[c];
+            for (int q = 0; q < 3; ++q) {
+                D.grid_kin[q] = gridh.kin[q];
+                D.grid_l0[q] = gridh.l0[q];
+            }
+            D.grid = 1;
+        }
         HIP_TRY(hipDeviceSynchronize());
         return CRONOS_OK;
     }();
@@ -872,7 +1047,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     P.oz = sim->origin[2];
     // several lanes per mass exist for the compact table forms, one workgroup per block
     if (D.lanes > 1 && (D.resident || D.sp_rec || !(D.packed || D.narrow))) D.lanes = 1;
-    if (D.lanes > 1) persistent = 0;
+    if (D.lanes > 1 || D.grid) persistent = 0;
     if (persistent > 0) {
         int g = 0;
         hipError_t e = cronos::persistent_grid(D, P.exact, &g);
@@ -1117,15 +1292,69 @@ std::vector<RitzCluster> ritz_clusters(const std::vector<double>& a, const std::
 
 }  // namespace
 
-extern "C" cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
-                                                    uint64_t seed, double* omega, int32_t* n_found,
-                                                    int32_t* iterations) {
-    cronos::clear_error();
+namespace {
+
+cronos_status check_modes_args(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol, const double* omega,
+                               const int32_t* n_found) {
     if (!sim || !omega || !n_found) return fail(CRONOS_EINVAL, "natural_frequencies: NULL argument");
     if (n_modes < 1 || n_modes > 32) return fail(CRONOS_EINVAL, "natural_frequencies: n_modes must be in [1, 32]");
     if (max_iter < 2 * n_modes + 8 || max_iter > (1 << 24))
         return fail(CRONOS_EINVAL, "natural_frequencies: max_iter must be in [2 n_modes + 8, 2^24]");
     if (!(tol > 0.0 && tol < 1.0)) return fail(CRONOS_EINVAL, "natural_frequencies: tol must be in (0, 1)");
+    return CRONOS_OK;
+}
+
+// The Lanczos iteration of cronos_natural_frequencies on workspace m (every buffer of
+// ModesBuffers sized for sim and max_iter).
+cronos_status lanczos_frequencies(cronos_sim sim, cronos::ModesBuffers& m, int32_t n_modes, int32_t max_iter, double tol,
+                                  uint64_t seed, double* omega, int32_t* n_found, int32_t* iterations) {
+    const int64_t n = sim->d.n;
+    HIP_TRY(hipMemsetAsync(m.q[0], 0, 3 * n * sizeof(double), sim->stream));
+    if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
+    HIP_TRY(cronos::launch_modes_init(sim->d, sim->cur, m, seed, sim->stream));
+    std::vector<double> ha(max_iter), hb(max_iter);
+    int32_t k = 0, next = std::min<int32_t>(max_iter, std::max<int32_t>(64, 4 * n_modes + 16));
+    int32_t found = 0;
+    std::vector<double> best;
+    while (true) {
+        for (; k < next; ++k) HIP_TRY(cronos::launch_modes_iteration(sim->d, sim->cur, sim->p, m, k, sim->stream));
+        HIP_TRY(hipMemcpyAsync(ha.data(), m.alpha, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+        HIP_TRY(hipMemcpyAsync(hb.data(), m.beta, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+        HIP_TRY(hipStreamSynchronize(sim->stream));
+        for (int32_t i = 0; i < k; ++i)
+            if (!std::isfinite(ha[i]) || !std::isfinite(hb[i]))
+                return fail(CRONOS_ESTATE, "natural_frequencies: non-finite Lanczos coefficient at step %d", i);
+        const int64_t count = std::min<int64_t>(k, 2 * n_modes + 8);
+        std::vector<RitzCluster> cl = ritz_clusters(ha, hb, k, count);
+        // the converged prefix: every cluster up to it has an error within tol
+        int32_t conv = 0;
+        for (const RitzCluster& c : cl) {
+            if (c.err > tol * std::fabs(c.theta) && c.err > c.floor && !(hb[k - 1] == 0.0)) break;
+            ++conv;
+        }
+        found = std::min<int32_t>(conv, n_modes);
+        best.clear();
+        for (int32_t c = 0; c < found; ++c) best.push_back(cl[c].theta);
+        const bool exhausted = hb[k - 1] <= 1e-14 * std::fabs(ha[0]) || k >= std::min<int64_t>(max_iter, 3 * n);
+        if (found >= n_modes || exhausted || k >= max_iter) break;
+        next = (int32_t)std::min<int64_t>(max_iter, (int64_t)k + std::max<int64_t>(256, k / 4));
+    }
+    for (int32_t c = 0; c < n_modes; ++c) {
+        const double t = c < found ? best[c] : 0.0;
+        omega[c] = t >= 0.0 ? std::sqrt(t) : -std::sqrt(-t);
+    }
+    *n_found = found;
+    if (iterations) *iterations = k;
+    return CRONOS_OK;
+}
+
+}  // namespace
+
+extern "C" cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_modes, int32_t max_iter, double tol,
+                                                    uint64_t seed, double* omega, int32_t* n_found,
+                                                    int32_t* iterations) {
+    cronos::clear_error();
+    TRY(check_modes_args(sim, n_modes, max_iter, tol, omega, n_found));
     const int64_t n = sim->d.n;
     HIP_TRY(hipSetDevice(sim->device));
     cronos::ModesBuffers m;
@@ -1146,47 +1375,46 @@ extern "C" cronos_status cronos_natural_frequencies(cronos_sim sim, int32_t n_mo
         TRY(alloc(&m.part_u, nu));
         TRY(alloc(&m.alpha, max_iter));
         TRY(alloc(&m.beta, max_iter));
-        HIP_TRY(hipMemsetAsync(m.q[0], 0, 3 * n * sizeof(double), sim->stream));
-        if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
-        HIP_TRY(cronos::launch_modes_init(sim->d, sim->cur, m, seed, sim->stream));
-        std::vector<double> ha(max_iter), hb(max_iter);
-        int32_t k = 0, next = std::min<int32_t>(max_iter, std::max<int32_t>(64, 4 * n_modes + 16));
-        int32_t found = 0;
-        std::vector<double> best;
-        while (true) {
-            for (; k < next; ++k) HIP_TRY(cronos::launch_modes_iteration(sim->d, sim->cur, sim->p, m, k, sim->stream));
-            HIP_TRY(hipMemcpyAsync(ha.data(), m.alpha, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
-            HIP_TRY(hipMemcpyAsync(hb.data(), m.beta, k * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
-            HIP_TRY(hipStreamSynchronize(sim->stream));
-            for (int32_t i = 0; i < k; ++i)
-                if (!std::isfinite(ha[i]) || !std::isfinite(hb[i]))
-                    return fail(CRONOS_ESTATE, "natural_frequencies: non-finite Lanczos coefficient at step %d", i);
-            const int64_t count = std::min<int64_t>(k, 2 * n_modes + 8);
-            std::vector<RitzCluster> cl = ritz_clusters(ha, hb, k, count);
-            // the converged prefix: every cluster up to it has an error within tol
-            int32_t conv = 0;
-            for (const RitzCluster& c : cl) {
-                if (c.err > tol * std::fabs(c.theta) && c.err > c.floor && !(hb[k - 1] == 0.0)) break;
-                ++conv;
-            }
-            found = std::min<int32_t>(conv, n_modes);
-            best.clear();
-            for (int32_t c = 0; c < found; ++c) best.push_back(cl[c].theta);
-            const bool exhausted = hb[k - 1] <= 1e-14 * std::fabs(ha[0]) || k >= std::min<int64_t>(max_iter, 3 * n);
-            if (found >= n_modes || exhausted || k >= max_iter) break;
-            next = (int32_t)std::min<int64_t>(max_iter, (int64_t)k + std::max<int64_t>(256, k / 4));
-        }
-        for (int32_t c = 0; c < n_modes; ++c) {
-            const double t = c < found ? best[c] : 0.0;
-            omega[c] = t >= 0.0 ? std::sqrt(t) : -std::sqrt(-t);
-        }
-        *n_found = found;
-        if (iterations) *iterations = k;
-        return CRONOS_OK;
+        return lanczos_frequencies(sim, m, n_modes, max_iter, tol, seed, omega, n_found, iterations);
     };
     const cronos_status st = run();
     (void)hipStreamSynchronize(sim->stream);
     for (void* p : owned) (void)hipFree(p);
+    return st;
+}
+
+extern "C" cronos_status cronos_natural_frequencies_noalloc(cronos_sim sim, int32_t n_modes, int32_t max_iter,
+                                                            double tol, uint64_t seed, double* omega,
+                                                            int32_t* n_found, int32_t* iterations) {
+    cronos::clear_error();
+    TRY(check_modes_args(sim, n_modes, max_iter, tol, omega, n_found));
+    const int64_t n = sim->d.n;
+    HIP_TRY(hipSetDevice(sim->device));
+    double* base = nullptr;
+    HIP_TRY(cronos::modes_scratch(sim->device, &base));
+    // carve the fixed workspace: every buffer starts on a 256-byte boundary
+    const int64_t counts[8] = {n, 3 * n, 3 * n, 3 * n, sim->d.nblk, (n + 255) / 256, max_iter, max_iter};
+    int64_t off[8], used = 0;
+    for (int b = 0; b < 8; ++b) {
+        off[b] = used;
+        used += (std::max<int64_t>(counts[b], 1) + 31) / 32 * 32;
+    }
+    if (used > (int64_t)cronos::kModesScratchDoubles)
+        return fail(CRONOS_EINVAL,
+                    "natural_frequencies_noalloc: %lld masses and max_iter %d need %lld doubles of workspace; the "
+                    "fixed workspace holds %zu",
+                    (long long)n, max_iter, (long long)used, cronos::kModesScratchDoubles);
+    cronos::ModesBuffers m;
+    m.ism = base + off[0];
+    m.q[0] = base + off[1];
+    m.q[1] = base + off[2];
+    m.y = base + off[3];
+    m.part_a = base + off[4];
+    m.part_u = base + off[5];
+    m.alpha = base + off[6];
+    m.beta = base + off[7];
+    const cronos_status st = lanczos_frequencies(sim, m, n_modes, max_iter, tol, seed, omega, n_found, iterations);
+    (void)hipStreamSynchronize(sim->stream);
     return st;
 }
 
@@ -1254,6 +1482,82 @@ void release(T*& p) {
 
 }  // namespace
 
+namespace {
+
+// The per-(workgroup, actuation group) layout of the adjoint's sensitivity sums: each
+// workgroup's distinct groups in increasing order get local indices 0, 1, ... (an entry's
+// index in lgrp) and consecutive slots; slot_ptr / slot_idx list every group's slots in
+// workgroup order.  Falls back to per-entry sums (red_groups = 0) when a workgroup holds more
+// than 255 groups or the LDS columns would exceed 64 KiB.
+cronos_status build_group_sums(cronos_sim_t* sim) {
+    RolloutBuffers& R = sim->ro;
+    const cronos::Layout& L = sim->lay;
+    const int32_t G = sim->d.n_factor;
+    const int64_t spb = L.block / cronos::kSlice, entries = L.slice_ptr.back();
+    std::vector<uint8_t> lg((size_t)entries, 0);
+    std::vector<int2> br((size_t)L.nblk);
+    std::vector<int32_t> gid;   // global group of each slot
+    int32_t most = 0;
+    std::vector<int32_t> local((size_t)std::max(G, 1), -1);
+    for (int64_t b = 0; b < L.nblk; ++b) {
+        const int64_t e0 = L.slice_ptr[b * spb], e1 = L.slice_ptr[(b + 1) * spb];
+        std::vector<int32_t> used;
+        for (int64_t e = e0; e < e1; ++e)
+            if (sim->h_grp[e] < G && local[sim->h_grp[e]] < 0) {
+                local[sim->h_grp[e]] = 0;
+                used.push_back(sim->h_grp[e]);
+            }
+        std::sort(used.begin(), used.end());
+        for (size_t q = 0; q < used.size(); ++q) local[used[q]] = (int32_t)q;
+        for (int64_t e = e0; e < e1; ++e)
+            if (sim->h_grp[e] < G) lg[(size_t)e] = (uint8_t)std::min<int32_t>(local[sim->h_grp[e]], 255);
+        br[(size_t)b] = make_int2((int)used.size(), (int)gid.size());
+        gid.insert(gid.end(), used.begin(), used.end());
+        most = std::max<int32_t>(most, (int32_t)used.size());
+        for (int32_t g : used) local[g] = -1;
+    }
+    const size_t columns = (size_t)most * L.block * std::max(sim->d.lanes, 1) * sizeof(double2);
+    R.red_built = true;
+    if (most > 255 || columns > 64 * 1024 || gid.empty()) {
+        R.red_groups = 0;
+        return CRONOS_OK;
+    }
+    // slots of each group in workgroup order
+    std::vector<int32_t> ptr((size_t)G + 1, 0), idx(gid.size());
+    for (int32_t g : gid) ++ptr[(size_t)g + 1];
+    for (int32_t g = 0; g < G; ++g) ptr[(size_t)g + 1] += ptr[(size_t)g];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t q = 0; q < gid.size(); ++q) idx[(size_t)fill[(size_t)gid[q]]++] = (int32_t)q;
+    auto up = [&](auto** dst, const auto* src, size_t count) -> cronos_status {
+        TRY(ensure(dst, count));
+        HIP_TRY(hipMemcpy(*dst, src, count * sizeof(**dst), hipMemcpyHostToDevice));
+        return CRONOS_OK;
+    };
+    TRY(up(&R.lgrp, lg.data(), lg.size()));
+    TRY(up(&R.blk_red, br.data(), br.size()));
+    TRY(up(&R.slot_ptr, ptr.data(), ptr.size()));
+    TRY(up(&R.slot_idx, idx.data(), idx.size()));
+    TRY(ensure(&R.acc, gid.size()));
+    TRY(ensure(&R.gsum, (size_t)G));
+    R.red_slots = (int32_t)gid.size();
+    R.red_groups = most;
+    return CRONOS_OK;
+}
+
+cronos::AdjSens adj_sens(const RolloutBuffers& R) {
+    cronos::AdjSens a;
+    a.sens = R.sens;
+    if (R.red_groups > 0) {
+        a.lgrp = R.lgrp;
+        a.blk_red = R.blk_red;
+        a.acc = R.acc;
+        a.red_groups = R.red_groups;
+    }
+    return a;
+}
+
+}  // namespace
+
 extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t ckpt_every, const double* loss_w,
                                         double* loss) {
     cronos::clear_error();
@@ -1297,6 +1601,7 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
         TRY(ensure(&R.xbl[q], 3 * n));
     }
     TRY(ensure(&R.sens, (size_t)sim->lay.slice_ptr.back()));
+    if (sim->actuated && !R.red_built) TRY(build_group_sums(sim));
     // loss weights in the device order (FP32)
     std::vector<float> hw(3 * n);
     for (int64_t i = 0; i < n; ++i)
@@ -1390,7 +1695,7 @@ cronos_status enqueue_reverse_sweep(cronos_sim_t* sim) {
                 nx.vb0 = R.vb[cur];
                 nx.xbl = R.xbl[wc ^ 1];
             }
-            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x[p] + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], R.sens,
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x[p] + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], adj_sens(R),
                                               std::cos(sim->omega * t), std::sin(sim->omega * t), st,
                                               sim->actuated ? R.seg_f[p] + (size_t)k * fs : nullptr, sim->p, nx));
             cur ^= 1;
@@ -1415,7 +1720,8 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     HIP_TRY(hipSetDevice(sim->device));
     HIP_TRY(hipMemcpyAsync(R.xb[0], R.lossw, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(R.vb[0], 0, 3 * n * sizeof(float), st));
-    HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
+    if (R.red_groups > 0) HIP_TRY(hipMemsetAsync(R.acc, 0, (size_t)R.red_slots * sizeof(double2), st));
+    else HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
     // the reverse sweep flips the adjoint buffers once per step
     const int cur = (int)(R.T & 1);
     if (sim->use_graph) {
@@ -1423,7 +1729,8 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
                                          (double)(sim->cycles >> 32), (double)(sim->cycles & 0xFFFFFFFFull), sim->omega,
                                          (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x[0], (double)(uintptr_t)R.seg_x[1],
                                          (double)(uintptr_t)R.seg_f[0], (double)(uintptr_t)R.seg_f[1],
-                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens};
+                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens,
+                                         (double)(uintptr_t)R.acc, (double)R.red_groups};
         if (!R.bwd_graph || R.bwd_key != key) {
             if (R.bwd_graph) {
                 HIP_TRY(hipStreamSynchronize(st));
@@ -1454,15 +1761,27 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     // per-group reduction of the actuation sensitivities, FP64, in entry order
     const int32_t G = sim->d.n_factor;
     if ((dphase || damp) && G > 0 && sim->actuated) {
-        std::vector<double2> hs(entries);
-        HIP_TRY(hipMemcpyAsync(hs.data(), R.sens, entries * sizeof(double2), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
         std::vector<double> sp(G, 0.0), sq(G, 0.0);
-        for (int64_t e = 0; e < entries; ++e) {
-            const uint16_t g = sim->h_grp[e];
-            if (g < G) {
-                sp[g] += hs[e].x;
-                sq[g] += hs[e].y;
+        if (R.red_groups > 0) {
+            // per group: its workgroup sums in workgroup order, on the device
+            HIP_TRY(cronos::launch_adj_group_sums(R.acc, R.slot_ptr, R.slot_idx, G, R.gsum, st));
+            std::vector<double2> hs(G);
+            HIP_TRY(hipMemcpyAsync(hs.data(), R.gsum, (size_t)G * sizeof(double2), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int32_t g = 0; g < G; ++g) {
+                sp[g] = hs[g].x;
+                sq[g] = hs[g].y;
+            }
+        } else {
+            std::vector<double2> hs(entries);
+            HIP_TRY(hipMemcpyAsync(hs.data(), R.sens, entries * sizeof(double2), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int64_t e = 0; e < entries; ++e) {
+                const uint16_t g = sim->h_grp[e];
+                if (g < G) {
+                    sp[g] += hs[e].x;
+                    sq[g] += hs[e].y;
+                }
             }
         }
         for (int32_t g = 0; g < G; ++g) {
@@ -1501,7 +1820,8 @@ extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_mas
     if (persistent_groups) *persistent_groups = sim->d.persistent_groups;
     if (lanes_per_mass) *lanes_per_mass = sim->d.lanes;
     if (step_form)
-        *step_form = sim->d.resident ? CRONOS_FORM_RESIDENT
+        *step_form = sim->d.grid ? CRONOS_FORM_GRID
+                     : sim->d.resident ? CRONOS_FORM_RESIDENT
                      : sim->d.sp_rec ? CRONOS_FORM_SPLIT
                      : sim->d.narrow ? CRONOS_FORM_NARROW
                      : sim->d.packed ? CRONOS_FORM_TABLE
@@ -1544,6 +1864,7 @@ extern "C" cronos_status cronos_autotune(const cronos_desc* d, int32_t n_steps, 
                 if (!pers || pgrid > 0) cfgs.push_back({bt, pers, 1});
         for (int ln : {2, 4})
             if (lanes_ok && blk * ln <= 1024) cfgs.push_back({4, 0, ln});
+        if (sim->d.grid) cfgs.assign(1, {4, 0, 1});   // the structured-box form has no such choices
         for (const auto& cfg : cfgs) {
             const int bt = cfg[0], pers = cfg[1], ln = cfg[2];
             {

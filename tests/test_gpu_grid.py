@@ -1,0 +1,155 @@
+"""The structured-box step form (a full grid of masses linked to all 26 neighbours, one
+workgroup per aligned 8 x 8 x 8 cube, no incidence data) against the FP64 oracle and against
+the general forms (run on an MI355X).  It sums each mass's springs in a fixed direction order
+instead of the CSR order, so it equals the other forms to rounding, not bitwise."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import physics as P
+from paper_2207_09334_amd import cronos as CR
+from paper_2207_09334_amd import problem as PR
+from tests.gpu_common import as_f32, force_scale, oracle_problem, position_error, say
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+X_TOL = 1e-4
+
+
+def _step_forces(sim, w, lat, xg, n):
+    """m v' / dt after one step from (xg, v = 0) at step n: the step's own total force (no
+    damping, no contact friction acting on a zero velocity)."""
+    CR.cronos_set_state(sim, xg, np.zeros_like(xg), n)
+    CR.cronos_step(sim, 1)
+    _, v1, _ = CR.cronos_read_state(sim)
+    inv_m = (1.0 / lat.mass).astype(np.float32).astype(np.float64)
+    return (v1 / float(np.float32(w.dt))) / inv_m[:, None]
+
+
+def _pair(w, steps, every=100, flags=0, x0=None, v0=None, start=0):
+    lat, sys_, ox0 = oracle_problem(w)
+    x0 = ox0 if x0 is None else x0
+    v0 = np.zeros_like(x0) if v0 is None else v0
+    sim, _, _ = PR.create(w, x0=x0, v0=v0, flags=flags | CR.CHECK_LAYOUT, block_masses=512)
+    form = CR.cronos_launch_config(sim)["step_form"]
+    if start:
+        CR.cronos_set_state(sim, x0, v0, start)
+    x, v = x0.copy(), v0.copy()
+    worst = 0.0
+    for n in range(start, start + steps, every):
+        x, v = P.run(sys_, x, v, n, every)
+        CR.cronos_step(sim, every)
+        xg, _, step = CR.cronos_read_state(sim)
+        assert step == n + every and np.isfinite(xg).all()
+        worst = max(worst, position_error(xg, x))
+    sim.close()
+    return worst, form
+
+
+def test_grid_form_is_chosen_only_for_full_boxes():
+    cases = [(W.cantilever(16, 8, 8), 0, 512, "grid"), (W.cantilever(16, 8, 8), CR.NO_GRID, 512, "narrow"),
+             (W.cantilever(16, 8, 8), 0, 256, "narrow"), (W.cantilever(20, 8, 8), 0, 512, "narrow"),
+             (W.cube_drop(16), 0, 512, "grid"), (W.cube_drop(16), CR.SPLIT, 512, "split")]
+    for w, flags, blk, want in cases:
+        sim, _, _ = PR.create(w, flags=flags, block_masses=blk)
+        got = CR.cronos_launch_config(sim)["step_form"]
+        say(f"  {w.name} block {blk} flags {flags:#x}: {got}")
+        assert got == want
+        sim.close()
+    # actuated bodies never take it
+    q = W.quadruped()
+    sim, _, _ = PR.create(q, block_masses=512)
+    assert CR.cronos_launch_config(sim)["step_form"] != "grid"
+    sim.close()
+
+
+def test_grid_step_forces_jittered_cube():
+    """A jittered 16^3 cube (strained springs, uniform k, every boundary class) held above the
+    plane: the step's own forces within 1e-5 of S_i of the oracle's."""
+    w = W.cube_drop(16)
+    lat, sys_, x0 = oracle_problem(w)
+    sim, _, _ = PR.create(w, x0=x0, block_masses=512)
+    assert CR.cronos_launch_config(sim)["step_form"] == "grid"
+    xg, _, _ = CR.cronos_read_state(sim)
+    f_dev = _step_forces(sim, w, lat, xg, 0)
+    s32 = as_f32(sys_)
+    f_ref = P.forces(s32, xg, 0.0)
+    err = np.linalg.norm(f_dev - f_ref, axis=1) / force_scale(s32, xg, 0.0)
+    say(f"  16^3 jittered cube: step force err {err.max():.3e}")
+    assert err.max() <= F_TOL
+    sim.close()
+
+
+def test_grid_positions_cantilever_1000():
+    """A 32x16x8 cantilever (fixed face, per-voxel stiffness with its boundary classes) under
+    gravity: 1000 steps within 1e-4 of the bbox of the oracle's trajectory."""
+    worst, form = _pair(W.cantilever(32, 16, 8), 1000)
+    say(f"  32x16x8 cantilever ({form}): position err {worst:.3e}")
+    assert form == "grid" and worst <= X_TOL
+
+
+def test_grid_positions_cube_free_fall_and_contact():
+    """The 16^3 cube drop: free fall over steps 0-1000, then a 1000-step window with contact
+    and friction from the device's state at step 6000 (wavefronts near z = 0 take exact
+    differences)."""
+    w = W.cube_drop(16)
+    worst, form = _pair(w, 1000)
+    say(f"  16^3 cube steps 0-1000 ({form}): position err {worst:.3e}")
+    assert form == "grid" and worst <= X_TOL
+    lat, sys_, x0 = oracle_problem(w)
+    sim, _, _ = PR.create(w, x0=x0, block_masses=512)
+    CR.cronos_step(sim, 6000)
+    xs, vs, _ = CR.cronos_read_state(sim)
+    sim.close()
+    assert xs[:, 2].min() < 0.0, "the cube should be touching the plane by step 6000"
+    worst, form = _pair(w, 1000, x0=xs, v0=vs, start=6000)
+    say(f"  16^3 cube contact window 6000-7000 ({form}): position err {worst:.3e}")
+    assert worst <= X_TOL
+
+
+def test_grid_verlet_matches_oracle():
+    """Verlet (eqs. (5)-(6)) on the structured-box form: 500 steps of the 16^3 cube drop
+    within 1e-4 of the bbox of the oracle's position-form Verlet."""
+    w = W.cube_drop(16)
+    lat, sys_, x0 = oracle_problem(w)
+    sim, _, _ = PR.create(w, x0=x0, block_masses=512, flags=CR.VERLET)
+    assert CR.cronos_launch_config(sim)["step_form"] == "grid"
+    x_prev, x = x0, P.verlet_start(sys_, x0, np.zeros_like(x0), 0)
+    n = 1
+    CR.cronos_step(sim, 1)
+    worst = 0.0
+    for target in (100, 300, 500):
+        while n < target:
+            x_prev, x = x, P.verlet_step(sys_, x_prev, x, n)
+            n += 1
+        CR.cronos_step(sim, target - CR.cronos_info(sim)["step"])
+        xg, _, step = CR.cronos_read_state(sim)
+        assert step == target
+        worst = max(worst, position_error(xg, x))
+    say(f"  16^3 cube, Verlet: position err {worst:.3e}")
+    assert worst <= X_TOL
+    sim.close()
+
+
+def test_grid_against_general_form_full_cantilever_and_repeatable():
+    """The full 400x40x40 cantilever, 300 steps: the structured-box form and the 16-bit-entry
+    form differ only by summation order (far below the position bar), and the structured-box
+    form is bitwise repeatable run to run."""
+    w = W.cantilever()
+    lat = PR.build_lattice(w)
+    outs = []
+    for flags in (0, 0, CR.NO_GRID):
+        sim, _, _ = PR.create(w, lat=lat, flags=flags, block_masses=512)
+        form = CR.cronos_launch_config(sim)["step_form"]
+        CR.cronos_step(sim, 300)
+        xg, vg, _ = CR.cronos_read_state(sim)
+        assert np.isfinite(xg).all()
+        outs.append((form, xg, vg))
+        sim.close()
+    forms = [o[0] for o in outs]
+    assert forms == ["grid", "grid", "narrow"]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    diff = position_error(outs[0][1], outs[2][1])
+    say(f"  400x40x40, 300 steps: grid vs 16-bit form position difference {diff:.3e} of the bbox")
+    assert diff <= 1e-6

@@ -101,7 +101,8 @@ def _step_forces(sim, w, lat, xg, n):
 
 def test_step_forces_cantilever_full_size_benchmarked_form():
     """The benchmarked kernel at the benchmarked size: the 400x40x40 cantilever created with
-    the defaults (16-bit entries, 512-mass workgroups, HIP graphs), stepped 200 steps from rest
+    the defaults (the structured-box form: 512-mass workgroups that are aligned 8 x 8 x 8
+    cubes, no incidence data, HIP graphs), stepped 200 steps from rest
     under gravity (a sagging, nearly relaxed lattice: elongations of ~1e-7 m, where the
     elongation arithmetic matters), then one step from that state with v = 0: the step's own
     total force m v'/dt on every free mass within 1e-5 of S_i of the oracle's, fed the device's
@@ -112,7 +113,7 @@ def test_step_forces_cantilever_full_size_benchmarked_form():
     sim, _, _ = PR.create(w, x0=x0)
     cfg = CR.cronos_launch_config(sim)
     say(f"  launch {cfg}")
-    assert cfg["step_form"] == "narrow" and cfg["block_masses"] == 512 and cfg["lanes_per_mass"] == 1
+    assert cfg["step_form"] == "grid" and cfg["block_masses"] == 512 and cfg["lanes_per_mass"] == 1
     CR.cronos_step(sim, 200)
     xg, _, n = CR.cronos_read_state(sim)
     f_dev = _step_forces(sim, w, lat, xg, n)
@@ -129,8 +130,9 @@ def test_step_forces_cantilever_full_size_benchmarked_form():
 
 
 def test_cantilever_full_size_step_forms_bitwise_equal():
-    """The full cantilever in the benchmarked form (16-bit entries) against the 32-bit entries
-    and the explicit per-entry (k, L0) form at the same 512-mass workgroups: bitwise the same
+    """The full cantilever with 16-bit entries (the default without the structured-box form)
+    against the 32-bit entries and the explicit per-entry (k, L0) form at the same 512-mass
+    workgroups: bitwise the same
     states after 100 steps (the same per-spring arithmetic in the same order), so the
     encodings and halo lists at this size (the 16-bit split of slot and pair bits) lose
     nothing."""
@@ -138,7 +140,7 @@ def test_cantilever_full_size_step_forms_bitwise_equal():
     say("case: cantilever 400x40x40, 100 steps: narrow / table / explicit, 512-mass workgroups")
     lat = PR.build_lattice(w)
     outs, forms = [], []
-    for flags in (0, CR.WIDE_ENTRIES, CR.NO_TABLE):
+    for flags in (CR.NO_GRID, CR.WIDE_ENTRIES, CR.NO_TABLE):
         sim, _, _ = PR.create(w, lat=lat, flags=flags, block_masses=512)
         forms.append(CR.cronos_launch_config(sim)["step_form"])
         CR.cronos_step(sim, 100)
