@@ -429,7 +429,7 @@ def surrogate_bench(args) -> dict:
     G = 32
     Xtr, Dtr, Xte, Dte = [], [], [], []
     held_bodies, ph_c, am_c, body_of = [], [], [], []
-    sim_seconds, rollouts, noise_floor = 0.0, 0, None
+    sim_seconds, rollouts, noise_floor, noise_floor_x = 0.0, 0, None, None
     material_k = spacing = None
     for p in range(args.pools + args.held_pools):
         pool = SG.Pool(args.pool, seed=4, steps=5000, first_robot=p * args.pool)
@@ -448,7 +448,11 @@ def surrogate_bench(args) -> dict:
             # the simulator's own noise floor on this target: draw 0 again with every phase
             # moved by 1e-6 rad; the chaotic part of the displacement is beyond any predictor
             ph0, am0 = pool.actuation(0)
-            noise_floor = SG.rms_relative_error(pool.rollout(ph0 + 1e-6, am0), Dtr[0])
+            Dp = pool.rollout(ph0 + 1e-6, am0)
+            noise_floor = SG.rms_relative_error(Dp, Dtr[0])
+            # the same for the forward (x) component alone: how much of it the dynamics decide
+            # beyond what any predictor of the inputs could know
+            noise_floor_x = float(np.sqrt(((Dp[:, 0] - Dtr[0][:, 0]) ** 2).mean() / (Dtr[0][:, 0] ** 2).mean()))
         if held:
             held_bodies.extend(pool.workload.bodies)
         sim_seconds += pool.sim_seconds
@@ -506,6 +510,7 @@ def surrogate_bench(args) -> dict:
         "morphology_features_per_robot_s": (t1 - t0) / len(held_bodies),
         "rms_rel_error": err, "p95_rel_error": float(np.percentile(per, 95)),
         "rms_rel_error_constant_predictor": err_mean, "simulator_noise_floor": noise_floor,
+        "simulator_noise_floor_x": noise_floor_x,
         "train_loss": sur.train_loss,
         "train_seconds": sur.train_seconds, "flagged": int(flagged.sum()), "simulated_after_screen": int(len(chosen)),
         "top5pct_overlap": len(true_top & pred_top) / k, "top5pct_overlap_random": k / n_cand,

@@ -129,23 +129,13 @@ struct AdjNext {
     float* vb0 = nullptr;
     float* xbl = nullptr;
 };
-// Where the adjoint gather sums the actuated springs' rest-length sensitivities.  With
-// red_groups > 0, each workgroup sums its step's sensitivities per actuation group it touches
-// (lgrp: an entry's group index within its workgroup; blk_red[b] = (count, first slot)) in LDS
-// and adds them to acc[slot]; otherwise every entry accumulates its own in sens[entry].
-struct AdjSens {
-    double2* sens = nullptr;          // [entries]
-    const uint8_t* lgrp = nullptr;    // [entries]
-    const int2* blk_red = nullptr;    // [nblk]
-    double2* acc = nullptr;           // [slots]
-    int red_groups = 0;               // largest count of a workgroup (0: per-entry sums)
-};
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             const AdjSens& sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
                              const StepParams& p, const AdjNext& next);
-// Per actuation group g: gsum[g] = the sum of acc over the slots slot_idx[slot_ptr[g] ..
-// slot_ptr[g + 1]) in that order.
-hipError_t launch_adj_group_sums(const double2* acc, const int32_t* slot_ptr, const int32_t* slot_idx, int n_groups,
+// Per actuation group g: gsum[g] = the sum of the per-entry sensitivities sens[e] over the
+// group's entries grp_entries[grp_ptr[g] .. grp_ptr[g + 1]) (one workgroup per group, a
+// fixed summation order).
+hipError_t launch_adj_group_sums(const double2* sens, const int32_t* grp_ptr, const int32_t* grp_entries, int n_groups,
                                  double2* gsum, hipStream_t st);
 // Actuation factors of steps n0 .. n0 + steps - 1 in one launch, row k at out + k * stride.
 hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycles, long long n0, int steps,

@@ -1066,34 +1066,23 @@ adj_local_kernel(const float4* __restrict__ x, const float* __restrict__ vstar, 
 // accumulated by exactly one lane.  With nx.x set, the mass's x_bar then feeds adj_local of
 // the step before (every input of which is the mass's own), so one launch per reversed step
 // remains; nx.w and nx.xbl must not be the w and xbl this launch reads.
-// RED (actuated only): the sensitivities are summed per workgroup and actuation group (see
-// AdjSens): each thread adds its entries' terms to its own LDS column of per-group sums, then
-// each wavefront reduces whole groups (columns in thread order, then a fixed cross-lane tree)
-// and one lane adds the result to the group's slot in acc; every sum has a fixed order.
-template <bool ACT, int LPM, bool RED>
+template <bool ACT, int LPM>
 __global__ void __launch_bounds__(1024)
 adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, const float* __restrict__ xbl,
                   float* __restrict__ xb0, const int32_t* __restrict__ slice_ptr, const uint16_t* __restrict__ nbr,
                   const float2* __restrict__ kl, const uint16_t* __restrict__ grp,
                   const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx,
                   const uint16_t* __restrict__ lane_mass, const float* __restrict__ factor,
-                  AdjSens sa, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
-                  int block, int lds_slots, int stage_factors, int fac_slots, StepParams p, AdjNext nx) {
+                  double2* __restrict__ sens, int n_factor, double cos_t, double sin_t, int n, int nblk, int nslice,
+                  int block, int lds_slots, int stage_factors, StepParams p, AdjNext nx) {
     extern __shared__ float4 sx[];
     float4* sw = sx + lds_slots;
     float* sfac = reinterpret_cast<float*>(sw + lds_slots);   // the factor table, when staged
-    double2* red = reinterpret_cast<double2*>(sfac + fac_slots);   // RED: [count][blockDim.x]
-    double2* __restrict__ sens = sa.sens;
     const int b = logical_block(nblk);
     if (b >= nblk) return;
     const int base = b * block;
     const int t = threadIdx.x, nt = (int)blockDim.x;
     const int m = t / LPM, sub = t % LPM;
-    int2 br = make_int2(0, 0);
-    if (RED) {
-        br = sa.blk_red[b];
-        for (int g = 0; g < br.x; ++g) red[g * nt + t] = make_double2(0.0, 0.0);   // this thread's column
-    }
     const float* fac = factor;
     if (ACT && stage_factors) {   // small tables: one LDS copy per workgroup, no dependent global load
         for (int q = t; q <= n_factor; q += nt) sfac[q] = factor[q];
@@ -1127,7 +1116,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
     float ax = 0.f, ay = 0.f, az = 0.f;
     // one incidence: the spring's tangent stiffness applied to w_j - w_i, and (actuated) the
     // sensitivity of the loss to its rest length, accumulated in FP64
-    auto one = [&](int e, int slot, float2 c, int g, float f, double2 acc, int lg) {
+    auto one = [&](int e, int slot, float2 c, int g, float f, double2 acc) {
         const float l0 = ACT ? c.y * f : c.y;
         const float4 xj = sx[slot];
         const float4 wj = sw[slot];
@@ -1146,15 +1135,9 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
             az += k * (nz * ndw + tr * (dwz - nz * ndw));
             if (ACT && g < n_factor) {
                 const double q = 0.5 * (double)c.y * (double)k * (double)ndw;
-                if (RED) {
-                    double2& r = red[lg * nt + t];
-                    r.x += cos_t * q;
-                    r.y += sin_t * q;
-                } else {
-                    acc.x += cos_t * q;
-                    acc.y += sin_t * q;
-                    sens[e] = acc;
-                }
+                acc.x += cos_t * q;
+                acc.y += sin_t * q;
+                sens[e] = acc;
             }
         }
     };
@@ -1168,7 +1151,7 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
         const int rows = (wdt - sub + LPM - 1) / LPM;
         int k = 0;
         for (; k + B <= rows; k += B) {
-            int slot[B], g[B], lg[B];
+            int slot[B], g[B];
             float2 c[B];
             float f[B];
             double2 acc[B];
@@ -1178,43 +1161,17 @@ adj_gather_kernel(const float4* __restrict__ x, const float4* __restrict__ w, co
                 slot[u] = nbr[e];
                 c[u] = kl[e];
                 g[u] = ACT ? (int)grp[e] : n_factor;
-                lg[u] = RED ? (int)sa.lgrp[e] : 0;
-                if (ACT && !RED) acc[u] = sens[e];
-                else acc[u] = make_double2(0.0, 0.0);
+                if (ACT) acc[u] = sens[e];
             }
 #pragma unroll
             for (int u = 0; u < B; ++u) f[u] = ACT ? fac[g[u]] : 1.0f;
 #pragma unroll
-            for (int u = 0; u < B; ++u)
-                one(e0 + ((k + u) * LPM + sub) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u], lg[u]);
+            for (int u = 0; u < B; ++u) one(e0 + ((k + u) * LPM + sub) * 64 + lane, slot[u], c[u], g[u], f[u], acc[u]);
         }
         for (; k < rows; ++k) {
             const int e = e0 + (k * LPM + sub) * 64 + lane;
             const int g = ACT ? (int)grp[e] : n_factor;
-            one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT && !RED ? sens[e] : make_double2(0.0, 0.0),
-                RED ? (int)sa.lgrp[e] : 0);
-        }
-    }
-    if (RED) {
-        __syncthreads();
-        const int wv = t >> 6, ln = t & 63, nw = nt >> 6;
-        for (int g = wv; g < br.x; g += nw) {
-            double sx_ = 0.0, sy_ = 0.0;
-            for (int q = ln; q < nt; q += 64) {
-                const double2 r = red[g * nt + q];
-                sx_ += r.x;
-                sy_ += r.y;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                sx_ += __shfl_xor(sx_, o, 64);
-                sy_ += __shfl_xor(sy_, o, 64);
-            }
-            if (ln == 0) {
-                double2 a = sa.acc[br.y + g];
-                a.x += sx_;
-                a.y += sy_;
-                sa.acc[br.y + g] = a;
-            }
+            one(e, nbr[e], kl[e], g, ACT ? fac[g] : 1.0f, ACT ? sens[e] : make_double2(0.0, 0.0));
         }
     }
 #pragma unroll
@@ -1567,62 +1524,65 @@ hipError_t launch_actuation_steps(const DeviceArrays& d, unsigned long long cycl
 }
 
 hipError_t launch_adj_gather(const DeviceArrays& d, const float4* x, const float4* w, const float* xbl, float* xb0,
-                             const AdjSens& sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
+                             double2* sens, double cos_t, double sin_t, hipStream_t st, const float* factor,
                              const StepParams& p, const AdjNext& next) {
     if (!factor) factor = d.factor;
-    // the factor table goes to LDS when small (kAdjStagedFactors entries at most); the per-group
-    // sums (RED) follow it at a 16-byte boundary
+    // the factor table goes to LDS when small (kAdjStagedFactors entries at most)
     const int stage = d.grp && d.n_factor + 1 <= kAdjStagedFactors ? 1 : 0;
-    const int fac_slots = stage ? (d.n_factor + 1 + 3) / 4 * 4 : 0;
+    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (stage ? (size_t)(d.n_factor + 1) * sizeof(float) : 0);
     const int lanes = d.lanes == 2 || d.lanes == 4 ? d.lanes : 1;
-    const int nt = d.block * lanes;
-    const bool red = d.grp && sens.red_groups > 0;
-    const size_t lds = 2 * (size_t)d.lds_slots * sizeof(float4) + (size_t)fac_slots * sizeof(float) +
-                       (red ? (size_t)sens.red_groups * nt * sizeof(double2) : 0);
-    const dim3 g(grid_for(d.nblk)), th((unsigned)nt);
+    const dim3 g(grid_for(d.nblk)), th((unsigned)(d.block * lanes));
     auto go = [&](auto k) {
         hipLaunchKernelGGL(k, g, th, lds, st, x, w, xbl, xb0, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr, d.halo_idx,
                            d.lane_mass, factor, sens, d.n_factor, cos_t, sin_t, (int)d.n, (int)d.nblk, (int)d.nslice,
-                           d.block, d.lds_slots, stage, fac_slots, p, next);
+                           d.block, d.lds_slots, stage, p, next);
     };
-    if (d.grp && red) {
-        if (lanes == 4) go(adj_gather_kernel<true, 4, true>);
-        else if (lanes == 2) go(adj_gather_kernel<true, 2, true>);
-        else go(adj_gather_kernel<true, 1, true>);
-    } else if (d.grp) {
-        if (lanes == 4) go(adj_gather_kernel<true, 4, false>);
-        else if (lanes == 2) go(adj_gather_kernel<true, 2, false>);
-        else go(adj_gather_kernel<true, 1, false>);
+    if (d.grp) {
+        if (lanes == 4) go(adj_gather_kernel<true, 4>);
+        else if (lanes == 2) go(adj_gather_kernel<true, 2>);
+        else go(adj_gather_kernel<true, 1>);
     } else {
-        if (lanes == 4) go(adj_gather_kernel<false, 4, false>);
-        else if (lanes == 2) go(adj_gather_kernel<false, 2, false>);
-        else go(adj_gather_kernel<false, 1, false>);
+        if (lanes == 4) go(adj_gather_kernel<false, 4>);
+        else if (lanes == 2) go(adj_gather_kernel<false, 2>);
+        else go(adj_gather_kernel<false, 1>);
     }
     return hipGetLastError();
 }
 
 namespace {
 
-__global__ void adj_group_sums_kernel(const double2* __restrict__ acc, const int32_t* __restrict__ slot_ptr,
-                                      const int32_t* __restrict__ slot_idx, int n_groups, double2* __restrict__ gsum) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_groups) return;
+// One workgroup per actuation group: its entries' sums, each thread over a strided part of
+// the group's entry list in order, then the fixed-order workgroup tree.
+__global__ void __launch_bounds__(256) adj_group_sums_kernel(const double2* __restrict__ sens,
+                                                             const int32_t* __restrict__ grp_ptr,
+                                                             const int32_t* __restrict__ grp_entries,
+                                                             double2* __restrict__ gsum) {
+    __shared__ double2 red[256];
+    const int g = blockIdx.x, t = threadIdx.x;
     double2 s = make_double2(0.0, 0.0);
-    for (int q = slot_ptr[g]; q < slot_ptr[g + 1]; ++q) {
-        const double2 a = acc[slot_idx[q]];
-        s.x += a.x;
-        s.y += a.y;
+    for (int q = grp_ptr[g] + t; q < grp_ptr[g + 1]; q += 256) {
+        const double2 v = sens[grp_entries[q]];
+        s.x += v.x;
+        s.y += v.y;
     }
-    gsum[g] = s;
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            red[t].x += red[t + h].x;
+            red[t].y += red[t + h].y;
+        }
+        __syncthreads();
+    }
+    if (t == 0) gsum[g] = red[0];
 }
 
 }  // namespace
 
-hipError_t launch_adj_group_sums(const double2* acc, const int32_t* slot_ptr, const int32_t* slot_idx, int n_groups,
+hipError_t launch_adj_group_sums(const double2* sens, const int32_t* grp_ptr, const int32_t* grp_entries, int n_groups,
                                  double2* gsum, hipStream_t st) {
     if (n_groups < 1) return hipSuccess;
-    hipLaunchKernelGGL(adj_group_sums_kernel, dim3((n_groups + 255) / 256), dim3(256), 0, st, acc, slot_ptr, slot_idx,
-                       n_groups, gsum);
+    hipLaunchKernelGGL(adj_group_sums_kernel, dim3(n_groups), dim3(256), 0, st, sens, grp_ptr, grp_entries, gsum);
     return hipGetLastError();
 }
 

@@ -77,17 +77,11 @@ struct RolloutBuffers {
     float* xb[2] = {nullptr, nullptr};
     float* vb[2] = {nullptr, nullptr};
     float* xbl[2] = {nullptr, nullptr};   // [3N] x_bar before the spring sum, alternating as w
-    double2* sens = nullptr;  // [entries] per-entry sensitivity sums (when the per-group ones do not fit)
-    // per-(workgroup, actuation group) sensitivity sums (see cronos::AdjSens), built once
-    bool red_built = false;
-    int32_t red_groups = 0;        // largest number of groups of a workgroup; 0: per-entry sums
-    int32_t red_slots = 0;
-    uint8_t* lgrp = nullptr;       // [entries]
-    int2* blk_red = nullptr;       // [nblk] (count, first slot)
-    double2* acc = nullptr;        // [slots]
-    int32_t* slot_ptr = nullptr;   // [n_factor + 1] slots of each group, in workgroup order
-    int32_t* slot_idx = nullptr;   // [slots]
-    double2* gsum = nullptr;       // [n_factor]
+    double2* sens = nullptr;  // [entries] each actuated entry's sensitivity, summed over the reversed steps
+    // the entries of each actuation group (CSR, entry order), for the per-group sums on the device
+    int32_t* grp_ptr = nullptr;      // [n_factor + 1]
+    int32_t* grp_entries = nullptr;  // [actuated entries]
+    double2* gsum = nullptr;         // [n_factor]
     size_t cap_seg = 0, cap_ck = 0;
     // the reverse sweep captured as one HIP graph, reused while everything it bakes in (the
     // rollout's extent, the buffers, the actuation frequency) is unchanged
@@ -141,7 +135,7 @@ void free_device(cronos_sim_t* s) {
     if (r.side) (void)hipStreamDestroy(r.side);
     void* rp[] = {r.seg_f[0], r.seg_f[1], r.ck_x, r.ck_v, r.seg_x[0], r.seg_x[1], r.seg_v[0], r.seg_v[1], r.seg_vs[0],
                   r.seg_vs[1], r.lossw, r.w[0], r.w[1], r.xb[0], r.xb[1], r.vb[0], r.vb[1],
-                  r.xbl[0], r.xbl[1], r.sens, r.lgrp, r.blk_red, r.acc, r.slot_ptr, r.slot_idx, r.gsum};
+                  r.xbl[0], r.xbl[1], r.sens, r.grp_ptr, r.grp_entries, r.gsum};
     for (void* p : rp)
         if (p) (void)hipFree(p);
     if (s->h_x) (void)hipHostFree(s->h_x);
@@ -1484,76 +1478,25 @@ void release(T*& p) {
 
 namespace {
 
-// The per-(workgroup, actuation group) layout of the adjoint's sensitivity sums: each
-// workgroup's distinct groups in increasing order get local indices 0, 1, ... (an entry's
-// index in lgrp) and consecutive slots; slot_ptr / slot_idx list every group's slots in
-// workgroup order.  Falls back to per-entry sums (red_groups = 0) when a workgroup holds more
-// than 255 groups or the LDS columns would exceed 64 KiB.
-cronos_status build_group_sums(cronos_sim_t* sim) {
+// The actuated entries of each actuation group in entry order (CSR over groups), read by the
+// device's per-group sums of the adjoint's sensitivities.
+cronos_status build_group_lists(cronos_sim_t* sim) {
     RolloutBuffers& R = sim->ro;
-    const cronos::Layout& L = sim->lay;
     const int32_t G = sim->d.n_factor;
-    const int64_t spb = L.block / cronos::kSlice, entries = L.slice_ptr.back();
-    std::vector<uint8_t> lg((size_t)entries, 0);
-    std::vector<int2> br((size_t)L.nblk);
-    std::vector<int32_t> gid;   // global group of each slot
-    int32_t most = 0;
-    std::vector<int32_t> local((size_t)std::max(G, 1), -1);
-    for (int64_t b = 0; b < L.nblk; ++b) {
-        const int64_t e0 = L.slice_ptr[b * spb], e1 = L.slice_ptr[(b + 1) * spb];
-        std::vector<int32_t> used;
-        for (int64_t e = e0; e < e1; ++e)
-            if (sim->h_grp[e] < G && local[sim->h_grp[e]] < 0) {
-                local[sim->h_grp[e]] = 0;
-                used.push_back(sim->h_grp[e]);
-            }
-        std::sort(used.begin(), used.end());
-        for (size_t q = 0; q < used.size(); ++q) local[used[q]] = (int32_t)q;
-        for (int64_t e = e0; e < e1; ++e)
-            if (sim->h_grp[e] < G) lg[(size_t)e] = (uint8_t)std::min<int32_t>(local[sim->h_grp[e]], 255);
-        br[(size_t)b] = make_int2((int)used.size(), (int)gid.size());
-        gid.insert(gid.end(), used.begin(), used.end());
-        most = std::max<int32_t>(most, (int32_t)used.size());
-        for (int32_t g : used) local[g] = -1;
-    }
-    const size_t columns = (size_t)most * L.block * std::max(sim->d.lanes, 1) * sizeof(double2);
-    R.red_built = true;
-    if (most > 255 || columns > 64 * 1024 || gid.empty()) {
-        R.red_groups = 0;
-        return CRONOS_OK;
-    }
-    // slots of each group in workgroup order
-    std::vector<int32_t> ptr((size_t)G + 1, 0), idx(gid.size());
-    for (int32_t g : gid) ++ptr[(size_t)g + 1];
+    const int64_t entries = sim->lay.slice_ptr.back();
+    std::vector<int32_t> ptr((size_t)G + 1, 0);
+    for (int64_t e = 0; e < entries; ++e)
+        if (sim->h_grp[e] < G) ++ptr[(size_t)sim->h_grp[e] + 1];
     for (int32_t g = 0; g < G; ++g) ptr[(size_t)g + 1] += ptr[(size_t)g];
-    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
-    for (size_t q = 0; q < gid.size(); ++q) idx[(size_t)fill[(size_t)gid[q]]++] = (int32_t)q;
-    auto up = [&](auto** dst, const auto* src, size_t count) -> cronos_status {
-        TRY(ensure(dst, count));
-        HIP_TRY(hipMemcpy(*dst, src, count * sizeof(**dst), hipMemcpyHostToDevice));
-        return CRONOS_OK;
-    };
-    TRY(up(&R.lgrp, lg.data(), lg.size()));
-    TRY(up(&R.blk_red, br.data(), br.size()));
-    TRY(up(&R.slot_ptr, ptr.data(), ptr.size()));
-    TRY(up(&R.slot_idx, idx.data(), idx.size()));
-    TRY(ensure(&R.acc, gid.size()));
-    TRY(ensure(&R.gsum, (size_t)G));
-    R.red_slots = (int32_t)gid.size();
-    R.red_groups = most;
+    std::vector<int32_t> idx((size_t)ptr[(size_t)G]), fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t e = 0; e < entries; ++e)
+        if (sim->h_grp[e] < G) idx[(size_t)fill[sim->h_grp[e]]++] = (int32_t)e;
+    TRY(ensure(&R.grp_entries, idx.size()));
+    TRY(ensure(&R.gsum, (size_t)std::max(G, 1)));
+    if (!idx.empty()) HIP_TRY(hipMemcpy(R.grp_entries, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    TRY(ensure(&R.grp_ptr, ptr.size()));
+    HIP_TRY(hipMemcpy(R.grp_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     return CRONOS_OK;
-}
-
-cronos::AdjSens adj_sens(const RolloutBuffers& R) {
-    cronos::AdjSens a;
-    a.sens = R.sens;
-    if (R.red_groups > 0) {
-        a.lgrp = R.lgrp;
-        a.blk_red = R.blk_red;
-        a.acc = R.acc;
-        a.red_groups = R.red_groups;
-    }
-    return a;
 }
 
 }  // namespace
@@ -1601,7 +1544,7 @@ extern "C" cronos_status cronos_rollout(cronos_sim sim, int64_t n_steps, int32_t
         TRY(ensure(&R.xbl[q], 3 * n));
     }
     TRY(ensure(&R.sens, (size_t)sim->lay.slice_ptr.back()));
-    if (sim->actuated && !R.red_built) TRY(build_group_sums(sim));
+    if (sim->actuated && !R.grp_ptr) TRY(build_group_lists(sim));
     // loss weights in the device order (FP32)
     std::vector<float> hw(3 * n);
     for (int64_t i = 0; i < n; ++i)
@@ -1695,7 +1638,7 @@ cronos_status enqueue_reverse_sweep(cronos_sim_t* sim) {
                 nx.vb0 = R.vb[cur];
                 nx.xbl = R.xbl[wc ^ 1];
             }
-            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x[p] + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], adj_sens(R),
+            HIP_TRY(cronos::launch_adj_gather(D, R.seg_x[p] + (size_t)k * n, R.w[wc], R.xbl[wc], R.xb[cur ^ 1], R.sens,
                                               std::cos(sim->omega * t), std::sin(sim->omega * t), st,
                                               sim->actuated ? R.seg_f[p] + (size_t)k * fs : nullptr, sim->p, nx));
             cur ^= 1;
@@ -1720,8 +1663,7 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     HIP_TRY(hipSetDevice(sim->device));
     HIP_TRY(hipMemcpyAsync(R.xb[0], R.lossw, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(R.vb[0], 0, 3 * n * sizeof(float), st));
-    if (R.red_groups > 0) HIP_TRY(hipMemsetAsync(R.acc, 0, (size_t)R.red_slots * sizeof(double2), st));
-    else HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
+    HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
     // the reverse sweep flips the adjoint buffers once per step
     const int cur = (int)(R.T & 1);
     if (sim->use_graph) {
@@ -1729,8 +1671,7 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
                                          (double)(sim->cycles >> 32), (double)(sim->cycles & 0xFFFFFFFFull), sim->omega,
                                          (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x[0], (double)(uintptr_t)R.seg_x[1],
                                          (double)(uintptr_t)R.seg_f[0], (double)(uintptr_t)R.seg_f[1],
-                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens,
-                                         (double)(uintptr_t)R.acc, (double)R.red_groups};
+                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens};
         if (!R.bwd_graph || R.bwd_key != key) {
             if (R.bwd_graph) {
                 HIP_TRY(hipStreamSynchronize(st));
@@ -1758,31 +1699,18 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     } else {
         TRY(enqueue_reverse_sweep(sim));
     }
-    // per-group reduction of the actuation sensitivities, FP64, in entry order
+    // per-group sums of the actuation sensitivities (FP64), then the chain rule to phase and amplitude
     const int32_t G = sim->d.n_factor;
     if ((dphase || damp) && G > 0 && sim->actuated) {
+        // per group: the sum of its entries' sensitivities, in a fixed order on the device
         std::vector<double> sp(G, 0.0), sq(G, 0.0);
-        if (R.red_groups > 0) {
-            // per group: its workgroup sums in workgroup order, on the device
-            HIP_TRY(cronos::launch_adj_group_sums(R.acc, R.slot_ptr, R.slot_idx, G, R.gsum, st));
-            std::vector<double2> hs(G);
-            HIP_TRY(hipMemcpyAsync(hs.data(), R.gsum, (size_t)G * sizeof(double2), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            for (int32_t g = 0; g < G; ++g) {
-                sp[g] = hs[g].x;
-                sq[g] = hs[g].y;
-            }
-        } else {
-            std::vector<double2> hs(entries);
-            HIP_TRY(hipMemcpyAsync(hs.data(), R.sens, entries * sizeof(double2), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            for (int64_t e = 0; e < entries; ++e) {
-                const uint16_t g = sim->h_grp[e];
-                if (g < G) {
-                    sp[g] += hs[e].x;
-                    sq[g] += hs[e].y;
-                }
-            }
+        HIP_TRY(cronos::launch_adj_group_sums(R.sens, R.grp_ptr, R.grp_entries, G, R.gsum, st));
+        std::vector<double2> hs(G);
+        HIP_TRY(hipMemcpyAsync(hs.data(), R.gsum, (size_t)G * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int32_t g = 0; g < G; ++g) {
+            sp[g] = hs[g].x;
+            sq[g] = hs[g].y;
         }
         for (int32_t g = 0; g < G; ++g) {
             const double ph = sim->h_phase.empty() ? 0.0 : sim->h_phase[g];

@@ -4,6 +4,8 @@ Bars: per-step force error max_i |df_i| / S_i <= 1e-5 with the oracle fed the de
 state and parameters; positions within 1e-4 of the bounding-box extent over 1000 steps with
 each side running from the same FP64 inputs (oracle FP64, device FP32); integer layouts
 bit-exact; repeated runs bitwise identical."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -230,27 +232,51 @@ def test_positions_quadruped_1000():
             assert e <= max(X_TOL, 10.0 * floor)
 
 
-def test_positions_quadruped_no_contact_1000():
-    """The actuated quadruped with the contact plane off (gravity on, damping as configured):
-    without contact the dynamics are not chaotic over 1000 steps, so the strict 1e-4 bar holds
-    at every 100th step; this separates the FP32 actuation factor and spring arithmetic (held
-    here) from the contact chaos that sets the FP32-state floor of the configured run."""
-    w = W.quadruped()
-    say("case: quadruped steps 0-1000, actuated, no contact plane")
+def _quadruped_no_contact(w, steps=1000):
+    """Every 100 steps of the quadruped without the plane: the device's error against the exact
+    oracle and the FP32-state envelope -- the larger deviation from it of two oracle runs that
+    store their state in FP32 after every step, one from the device's own FP32 start and one
+    from that start moved by one FP32 ulp on every coordinate (seeded signs)."""
     lat, _, x0 = oracle_problem(w)
     sys_ = P.system_from(lat, w, ground=False)
     sim, _, _ = PR.create(w, x0=x0, ground=False, flags=CR.CHECK_LAYOUT)
-    x, v = x0.copy(), np.zeros_like(x0)
-    worst = 0.0
-    for n in range(0, 1000, 100):
-        x, v = P.run(sys_, x, v, n, 100)
+    x_dev0, _, _ = CR.cronos_read_state(sim)
+    sign = np.where(np.random.default_rng(11).random(x_dev0.shape) < 0.5, -np.inf, np.inf)
+    x_ulp = np.nextafter(x_dev0.astype(np.float32), sign.astype(np.float32)).astype(np.float64)
+    xa, va = x0.copy(), np.zeros_like(x0)
+    runs = [(x_dev0.copy(), np.zeros_like(x0)), (x_ulp, np.zeros_like(x0))]
+    rows = []
+    for n in range(0, steps, 100):
+        xa, va = P.run(sys_, xa, va, n, 100)
+        runs = [run_fp32_state(sys_, xb, vb, n, 100) for xb, vb in runs]
         CR.cronos_step(sim, 100)
         xg, _, _ = CR.cronos_read_state(sim)
-        e = position_error(xg, x)
-        worst = max(worst, e)
-        say(f"  step {n + 100}: position err {e:.3e}")
-        assert e <= X_TOL
-    assert worst > 0.0
+        env = max(position_error(xb, xa) for xb, _ in runs)
+        rows.append((n + 100, position_error(xg, xa), env))
+        say(f"  step {n + 100}: device err {rows[-1][1]:.3e}, FP32-state envelope {env:.3e}")
+    sim.close()
+    return rows
+
+
+def test_positions_quadruped_no_contact_1000():
+    """The actuated quadruped with the contact plane off (gravity on, damping as configured).
+    At the configured amplitude (rest lengths +-20%) the actuated dynamics amplify rounding
+    without any contact as well: two FP64 runs that differ only by storing their state in
+    FP32 (one of them started one ulp away) leave the exact trajectory by more than 1e-4 of the
+    bbox within the 1000 steps, so the configured amplitude is held to 10x that envelope.  At
+    a tenth of the amplitude the same body is held to the strict 1e-4 bar at every 100th step:
+    the FP32 actuation factor and spring arithmetic are accurate, and the excess at full
+    amplitude is the sensitivity of the actuated dynamics, not contact."""
+    w = W.quadruped()
+    say("case: quadruped steps 0-1000, actuated (amplitude 0.2), no contact plane")
+    rows = _quadruped_no_contact(w)
+    for step, e, env in rows:
+        assert e <= max(X_TOL, 10.0 * env)
+    assert rows[-1][2] > X_TOL, "the FP32-state envelope should exceed the bar: sensitivity, not contact"
+    w2 = dataclasses.replace(w, amp=np.asarray(w.amp, float) * 0.1)
+    say("case: quadruped steps 0-1000, actuated (amplitude 0.02), no contact plane")
+    rows = _quadruped_no_contact(w2)
+    assert all(e <= X_TOL for _, e, _ in rows) and max(e for _, e, _ in rows) > 0.0
 
 
 def test_positions_cantilever_slab_1000():
