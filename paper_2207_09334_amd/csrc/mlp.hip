@@ -16,11 +16,12 @@
 // weights, so padded activations are exactly zero.
 //
 // Tiling: a workgroup of 4 wavefronts computes a 64 x 64 tile of C, each wavefront a 32 x 32
-// quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 64 (or 32) through two LDS buffers:
+// quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 128 (or 64, 32) through two LDS buffers:
 // the next K-step's operands are loaded into registers while the matrix cores work on the
 // current one, then stored to the other buffer (one barrier per K-step).  The weight
 // gradients (K = the minibatch rows) split K into chunks of 512 rows computed by separate
-// workgroups into FP32 partials that one more kernel sums in a fixed order.  Operand layouts
+// workgroups into FP32 partials, laid out like the parameters, that Adam adds in a fixed
+// order (or one more kernel, when the gradient itself is asked for).  Operand layouts
 // of the 16x16x32 BF16 MFMA: lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j]
 // [l % 16], j = 0..7, and receives C[4 (l / 16) + r][l % 16], r = 0..3.
 #include <hip/hip_runtime.h>
@@ -235,12 +236,15 @@ __device__ __forceinline__ void write_shadow(const ShadowMap& s, long i, float v
         }
 }
 
-// Adam on the FP32 master copy; refreshes the BF16 shadows of the weight entries.
-__global__ void adam_kernel(float* p, float* m, float* v, const float* grad, ShadowMap sm, long n, float lr, float b1,
-                            float b2, float eps, float c1, float c2) {
+// Adam on the FP32 master copy; refreshes the BF16 shadows of the weight entries.  The
+// gradient is the sum of `splits` partial gradients laid out like the parameters, `stride`
+// apart, added in split order (the order splitk_sum_kernel uses).
+__global__ void adam_kernel(float* p, float* m, float* v, const float* grad, int splits, long stride, ShadowMap sm,
+                            long n, float lr, float b1, float b2, float eps, float c1, float c2) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float gi = grad[i];
+    float gi = grad[i];
+    for (int z = 1; z < splits; ++z) gi += grad[z * stride + i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
@@ -321,8 +325,8 @@ struct cronos_mlp_t {
     bf16* dyt = nullptr;               // [sizes[4]][max_rows]
     bf16* dz[3] = {};                  // [rows][wp[l+1]]
     bf16* dzt[3] = {};                 // [sizes[l+1]][max_rows]
-    float* part_w = nullptr;           // split-K partials of the weight gradients
-    long part_stride = 0;
+    float* part_w = nullptr;           // [splits][n_params] split-K partials of the weight gradients
+    int grad_splits = 1;               // partials Adam adds (1: the gradient is in grad)
     double* part = nullptr;            // loss partials
     // training data
     float* data_x = nullptr;
@@ -337,7 +341,9 @@ template <int EPI>
 hipError_t gemm(hipStream_t st, GemmArgs g, int splits = 1) {
     dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, splits);
     if (splits == 1) g.k_chunk = g.K;
-    if (g.K % 64 == 0 && g.k_chunk % 64 == 0)
+    if (g.K % 128 == 0 && g.k_chunk % 128 == 0)
+        hipLaunchKernelGGL((gemm_kernel<EPI, 128>), grid, dim3(256), 0, st, g);
+    else if (g.K % 64 == 0 && g.k_chunk % 64 == 0)
         hipLaunchKernelGGL((gemm_kernel<EPI, 64>), grid, dim3(256), 0, st, g);
     else
         hipLaunchKernelGGL((gemm_kernel<EPI, 32>), grid, dim3(256), 0, st, g);
@@ -405,7 +411,9 @@ cronos_status forward_dev(cronos_mlp_t* q, int rows) {
 }
 
 // Loss and gradients for `rows` rows whose inputs are in q->x / q->xt and targets in q->t.
-cronos_status backward_dev(cronos_mlp_t* q, int rows) {
+// With more than one K-split the weight gradients stay as per-split partials (q->part_w,
+// laid out like the parameters) for Adam to add, unless sum_grads asks for them in q->grad.
+cronos_status backward_dev(cronos_mlp_t* q, int rows, bool sum_grads) {
     const int P = (rows + 63) / 64 * 64;
     const long R = q->max_rows;
     const int n_out = q->sizes[4];
@@ -434,13 +442,9 @@ cronos_status backward_dev(cronos_mlp_t* q, int rows) {
             g.Cf = q->grad + q->off_w[l];
             HIP_TRY(gemm<kPartial>(q->stream, g, 1));
         } else {
-            g.Cf = q->part_w;
-            g.part_stride = q->part_stride;
+            g.Cf = q->part_w + q->off_w[l];
+            g.part_stride = q->n_params;
             HIP_TRY(gemm<kPartial>(q->stream, g, splits));
-            const long n = (long)(K + 1) * N;
-            hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q->stream, q->part_w,
-                               q->part_stride, splits, q->grad + q->off_w[l], n);
-            HIP_TRY(hipGetLastError());
         }
         if (l) {
             // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1}) : (P x wp[l+1]) (wp[l+1] x wp[l])
@@ -463,6 +467,13 @@ cronos_status backward_dev(cronos_mlp_t* q, int rows) {
             dnext = q->dz[l - 1];
             dnext_t = q->dzt[l - 1];
         }
+    }
+    q->grad_splits = splits;
+    if (splits > 1 && sum_grads) {
+        hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((q->n_params + 255) / 256)), dim3(256), 0, q->stream,
+                           q->part_w, q->n_params, splits, q->grad, q->n_params);
+        HIP_TRY(hipGetLastError());
+        q->grad_splits = 1;
     }
     return CRONOS_OK;
 }
@@ -487,8 +498,10 @@ cronos_status upload_rows(cronos_mlp_t* q, const float* x, const float* t, int r
 cronos_status adam_dev(cronos_mlp_t* q, double lr, double b1, double b2, double eps) {
     q->step += 1;
     const float c1 = (float)(1.0 - std::pow(b1, q->step)), c2 = (float)(1.0 - std::pow(b2, q->step));
+    const bool parts = q->grad_splits > 1;
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((q->n_params + 255) / 256)), dim3(256), 0, q->stream, q->p, q->m,
-                       q->v, q->grad, q->smap, q->n_params, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
+                       q->v, parts ? q->part_w : q->grad, parts ? q->grad_splits : 1, q->n_params, q->smap,
+                       q->n_params, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
     HIP_TRY(hipGetLastError());
     return CRONOS_OK;
 }
@@ -580,12 +593,9 @@ extern "C" cronos_status cronos_mlp_create(const int32_t* sizes, const double* p
         HIP_TRY(dmalloc(&q->dy, R * q->wp[4]));
         HIP_TRY(dmalloc(&q->dyt, sizes[4] * R));
         HIP_TRY(dmalloc(&q->part, (R * q->wp[4] + 255) / 256));
-        // split-K partials of the largest weight gradient at max_rows rows
+        // split-K partials of the weight gradients at max_rows rows, laid out like the parameters
         const int splits = (int)((R + kSplitRows - 1) / kSplitRows);
-        long biggest = 0;
-        for (int l = 0; l < 4; ++l) biggest = std::max<long>(biggest, (long)(sizes[l] + 1) * sizes[l + 1]);
-        q->part_stride = biggest;
-        if (splits > 1) HIP_TRY(dmalloc(&q->part_w, (size_t)splits * biggest));
+        if (splits > 1) HIP_TRY(dmalloc(&q->part_w, (size_t)splits * n));
         // the appended row of ones of every transposed layer input
         auto ones = [&](bf16* base, int row) -> hipError_t {
             hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, q->stream, base + (long)row * R, R,
@@ -656,7 +666,7 @@ extern "C" cronos_status cronos_mlp_loss_grad(cronos_mlp q, const float* x, cons
     HIP_TRY(hipSetDevice(q->device));
     cronos_status st = upload_rows(q, x, t, rows);
     if (st == CRONOS_OK) st = forward_dev(q, rows);
-    if (st == CRONOS_OK) st = backward_dev(q, rows);
+    if (st == CRONOS_OK) st = backward_dev(q, rows, true);
     if (st != CRONOS_OK) return st;
     const double l = loss_from_parts(q, rows, &st);
     if (st != CRONOS_OK) return st;
@@ -721,7 +731,7 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
             const int r = (int)std::min<int64_t>(batch, rows - b0);
             cronos_status st = gather_rows(q, q->data_x, q->data_t, q->idx + b0, r);
             if (st == CRONOS_OK) st = forward_dev(q, r);
-            if (st == CRONOS_OK) st = backward_dev(q, r);
+            if (st == CRONOS_OK) st = backward_dev(q, r, false);
             const double lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * (double)step++ / (double)last));
             if (st == CRONOS_OK) st = adam_dev(q, lr_t, 0.9, 0.999, 1e-8);
             if (st != CRONOS_OK) return st;
