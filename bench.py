@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "spring-steps/sec + % HBM roofline; surrogate vs plain sim evals/sec"
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK = 256 * 2.4e9          # wave64 VALU instructions per second: 256 CUs x 2.4 GHz x 1 per CU
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cantilever_400x40x40.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_grid_kernel_cantilever_400x40x40.traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_09334_amd", "csrc", "kernels.hip")
 
 
