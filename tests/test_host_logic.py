@@ -82,3 +82,14 @@ def test_spectral_peak_recovers_a_known_frequency(f_true):
     z = (0.0973 + 4e-4 * np.cos(2 * np.pi * f_true * t + 0.3) + 3e-5 * np.sin(4 * np.pi * f_true * t)
          + 2e-6 * rng.standard_normal(t.size))
     assert bench.spectral_peak(z, h) == pytest.approx(f_true, rel=2e-3)
+
+
+def test_alu_roofline_cycle_count():
+    """The arithmetic roofline's per-step count: 2 incidences per spring, 19 full-rate VALU
+    instructions and 2 quarter-rate ones (4 cycles each) per incidence, 64 incidences per wave64
+    instruction; actuated springs add 3."""
+    import bench
+    assert bench.alu_cycles(8_020_476) == 2 * 8_020_476 * 27 / 64
+    assert bench.alu_cycles(100, actuated=True) == 2 * 100 * 30 / 64
+    assert bench.VALU_PEAK == 256 * 2.4e9
+
