@@ -8,8 +8,8 @@
   stiffness, 28-30 stiffness-weighted mean centre minus mean centre, 31 fraction of voxel
   faces without a neighbouring voxel;
 then (A_g cos phi_g, A_g sin phi_g) for every actuation group g.
-Parity unpinned beyond its definition: checked against the native featurizer and against
-hand-computed values for a single voxel and a 2x1x1 bar (tests/test_native_features.py).
+Pinned by hand-computed values: every field of a single voxel and of a three-voxel L (two arms,
+three materials, one passive voxel), in tests/test_native_features.py.
 """
 from __future__ import annotations
 

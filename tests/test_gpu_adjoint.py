@@ -198,6 +198,35 @@ def test_autograd_function_drives_torch():
     assert np.array_equal(phase.grad.numpy(), dp) and np.array_equal(amp.grad.numpy(), da)
 
 
+def test_graph_captured_sweep_follows_amplitude_increases_in_the_shifted_frame():
+    """Without the contact plane the device frame is shifted, so wavefronts take the plain
+    coordinate difference when all their masses lie beyond the safe distance, which grows with
+    the largest amplitude.  Raising the amplitudes between calls (0.02 -> 0.1 -> 0.25) must drop
+    the captured sweep along with the parameters it captured: every call's gradients equal the
+    plain launches' bit for bit."""
+    w = _actuated_cube(ground=False)
+    say("case: adjoint sweep graph vs plain launches in the shifted frame, amplitudes raised per call")
+    sim_g, lat, x0 = PR.create(w)
+    sim_p, _, _ = PR.create(w, flags=CR.NO_GRAPH)
+    lw = np.zeros_like(lat.x)
+    lw[:, 2] = lat.mass / lat.mass.sum()
+    for amp in (0.02, 0.1, 0.25):
+        am = np.full(len(w.amp), amp)
+        out = []
+        for sim in (sim_g, sim_p):
+            CR.cronos_set_state(sim, x0, np.zeros_like(x0), 0)
+            CR.cronos_set_actuation(sim, w.phase, am, w.freq_hz)
+            loss = CR.cronos_rollout(sim, 200, 50, lw)
+            dp, da = CR.cronos_rollout_backward(sim)
+            out.append((loss, dp, da))
+        say(f"  amplitude {amp}: loss {out[0][0]:.9e}, |dphase| {np.abs(out[0][1]).max():.3e}")
+        assert out[0][0] == out[1][0]
+        assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+        assert np.abs(out[0][1]).max() > 0
+    sim_g.close()
+    sim_p.close()
+
+
 def test_graph_captured_sweep_matches_plain_launches():
     """The reverse sweep is captured once as a HIP graph and replayed while the rollout's extent
     and frequency stay the same: over repeated calls with new phases and amplitudes between

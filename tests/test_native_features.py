@@ -51,6 +51,32 @@ def test_bar_by_hand():
     assert f[31] == pytest.approx(10 / 12)
 
 
+def test_l_shape_every_field_by_hand():
+    """Three voxels in an L (x and z arms, materials 0/1/2, groups 0/passive/1): every one of the
+    32 descriptors and the actuation pairs worked out by hand, for the oracle and the native
+    featurizer."""
+    b = W.Body(np.array([[0, 0, 0], [1, 0, 0], [0, 0, 1]]), np.array([0, 1, 2], np.int32),
+               np.array([0, -1, 1], np.int32))
+    ph, am = [0.4, 2.0], [0.25, 0.05]
+    e = np.zeros(36)
+    e[0] = math.log(16)                                  # 12 corners at z <= 1, 4 more at z = 2
+    e[1] = math.log(3)
+    e[2:5] = [2 * A, A, 2 * A]
+    e[5:8] = 1.0 / 3.0
+    e[8:11] = [-A / 6, 0.0, -A / 6]                      # mean centre (5/6, 1/2, 5/6) a minus (1, 1/2, 1) a
+    e[11:17] = [2 * A * A / 9, 0.0, 2 * A * A / 9, 0.0, -A * A / 9, 0.0]
+    e[17] = 2.0 / 3.0                                    # two voxels in the bottom layer
+    e[18] = 2.0 / 3.0                                    # height bins: z = 0 -> 0, z = 1 -> 8 * 1 // 2 = 4
+    e[22] = 1.0 / 3.0
+    e[26] = 2.0 / 3.0
+    e[27] = 4.0                                          # mean of 3, 4, 5
+    e[28:31] = [(65500.0 / 111000.0 - 5.0 / 6.0) * A, 0.0, (155500.0 / 111000.0 - 5.0 / 6.0) * A]
+    e[31] = 14.0 / 18.0                                  # 18 faces, two shared pairs
+    e[32:36] = [0.25 * math.cos(0.4), 0.25 * math.sin(0.4), 0.05 * math.cos(2.0), 0.05 * math.sin(2.0)]
+    np.testing.assert_allclose(F.features(b, K, A, ph, am), e, rtol=1e-13, atol=1e-18)
+    np.testing.assert_allclose(_native([b], ph, am)[0], e, rtol=1e-13, atol=1e-18)
+
+
 def test_native_matches_oracle_on_population():
     w = W.population(12, seed=4, lo=300, hi=5000)
     ph, am = W.population_actuation(4, 12, 32, draw=3)
