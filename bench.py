@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -579,6 +580,9 @@ def main(argv=None):
     ap.add_argument("--dump", default="", help="surrogate: directory to save the data set to (npz)")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--settle-ms", type=float, default=30.0,
+                    help="milliseconds of the same steps on a second copy of the workload before the warm-up, "
+                         "so that the timed steps run at the device's sustained clocks (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=2048, metavar="MIB",
                     help="before the timed steps, time the library's streaming copy and read kernels over "
                          "MIB MiB (the attainable-bandwidth reference and the reference kernel for the HBM "
@@ -619,7 +623,9 @@ def main(argv=None):
              (CR.VERLET if args.integrator == "verlet" else 0) | (CR.RESIDENT if args.resident else 0))
     if args.workload == "candidate":
         w = W.candidate_bar(args.points)
-        sim, *_ = PR.create_points(w, stream=stream.cuda_stream, flags=flags, block_masses=args.block)
+
+        def make():
+            return PR.create_points(w, stream=stream.cuda_stream, flags=flags, block_masses=args.block)[0]
         n_bodies, batched, actuated, lat = 1, False, False, None
     else:
         if args.workload == "population":
@@ -631,11 +637,15 @@ def main(argv=None):
         else:
             w = W.cantilever(args.nx, 40, 40)
         lat = PR.build_lattice(w)
-        sim, _, _ = PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
-                              batch=args.batch, lanes_per_mass=args.lanes, tune_steps=20 if args.tune else 0)
+
+        def make():
+            return PR.create(w, lat=lat, stream=stream.cuda_stream, flags=flags, block_masses=args.block,
+                             batch=args.batch, lanes_per_mass=args.lanes, tune_steps=20 if args.tune else 0)[0]
         n_bodies, batched, actuated = len(w.bodies), len(w.bodies) > 1, w.n_groups > 0
+    sim = make()
     info = CR.cronos_info(sim)
     launch = CR.cronos_launch_config(sim)
+    mode = CR.cronos_launch_mode(sim)
     N, S = info["n_masses"], info["n_springs"]
 
     copy_gbs = read_gbs = None
@@ -643,7 +653,34 @@ def main(argv=None):
         # the library's plain streaming kernels over a buffer of known size: the bandwidth a
         # hand-written HIP copy (read + write) and read pass reach on this device (best of 5)
         copy_gbs, read_gbs = CR.cronos_stream_bandwidth(args.calibrate_copy << 20, reps=5)
-    torch.cuda.synchronize()
+    # The device raises its clocks over milliseconds of sustained work and lowers them within
+    # milliseconds of idling, so a few steps timed right after a short warm-up from an idle
+    # device run slower than the same steps do in a long run.  A second copy of the workload
+    # measures that first (the same W warm-up and K timed steps, from idle: cold_ms_per_step),
+    # then runs its steps for --settle-ms; the timed simulation's W warm-up steps follow on the
+    # same stream with no idle gap, then the synchronised K timed steps.
+    settle = None
+    twin = None
+    if args.settle_ms > 0:
+        twin = make()
+        torch.cuda.synchronize()
+        CR.cronos_step(twin, args.warmup)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        CR.cronos_step(twin, args.steps)
+        c1.record(stream)
+        c1.synchronize()
+        cold_ms = c0.elapsed_time(c1)
+        probe = 16
+        c0.record(stream)
+        CR.cronos_step(twin, probe)
+        c1.record(stream)
+        c1.synchronize()
+        n_settle = max(1, int(math.ceil(args.settle_ms / (c0.elapsed_time(c1) / probe))))
+        CR.cronos_step(twin, n_settle)
+        settle = {"steps": probe + n_settle, "ms": args.settle_ms, "on": "a second copy of the workload",
+                  "cold_ms_per_step": cold_ms / args.steps}
     CR.cronos_step(sim, args.warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -655,6 +692,8 @@ def main(argv=None):
     end.synchronize()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
+    if twin is not None:
+        twin.close()
     x, v, step = CR.cronos_read_state(sim)
     import numpy as np
     if not np.isfinite(x).all():
@@ -674,7 +713,8 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n_bodies": n_bodies, "n_masses": N, "n_springs": S, "dt": w.dt,
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
-                   "persistent_groups": launch["persistent_groups"], "hip_graph": not args.no_graph,
+                   "persistent_groups": launch["persistent_groups"], "hip_graph": mode["hip_graph"],
+                   "plain_step_us_at_creation": mode["plain_step_us"],
                    "exact_difference": not args.fast_diff, "step_form": launch["step_form"],
                    "lanes_per_mass": launch["lanes_per_mass"],
                    "integrator": args.integrator},
@@ -709,6 +749,8 @@ def main(argv=None):
         rate = prof["valu_wave_instr_per_launch"] / sec_per_step
         out["valu_issue"] = {"achieved": rate, "peak": VALU_PEAK, "unit": "wave64 VALU instr/s",
                              "frac": rate / VALU_PEAK, "instr_per_launch": prof["valu_wave_instr_per_launch"]}
+    if settle is not None:
+        out["clock_settle"] = settle
     if batched:
         out["rollouts_per_s"] = len(w.bodies) / (w.steps * sec_per_step)
         out["rollout_steps"] = w.steps

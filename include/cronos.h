@@ -45,6 +45,10 @@ typedef enum {
 #define CRONOS_ALLOW_UNSTABLE 0x1u   /* skip the stability check at creation                 */
 #define CRONOS_CHECK_LAYOUT   0x2u   /* verify the device layout against the CSR at creation  */
 #define CRONOS_NO_GRAPH       0x4u   /* enqueue steps as plain launches, not HIP graphs      */
+#define CRONOS_GRAPH          0x800u /* enqueue steps as HIP graphs whatever the step time (by
+                                        default a step that takes 12 us or more with plain
+                                        launches keeps them; see cronos_launch_mode); not with
+                                        CRONOS_NO_GRAPH                                      */
 #define CRONOS_NO_TABLE       0x10u  /* keep explicit per-entry (k, L0) in the step instead of a
                                         16-bit index into the table of distinct pairs        */
 #define CRONOS_NO_SHIFT       0x20u  /* keep the caller's coordinate frame on the device (by
@@ -382,6 +386,19 @@ cronos_status cronos_info(cronos_sim sim, int64_t* n_masses, int64_t* n_springs,
                                    sums to rounding)                                              */
 cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_t* batch, int32_t* persistent_groups,
                                    int32_t* step_form, int32_t* lanes_per_mass);
+
+/* How cronos_step enqueues its steps (not in the paper).  At creation the step is timed with
+ * plain launches on the simulation's stream (9 launches that repeat one step from the current
+ * buffers into the other set, HIP events; the state is unchanged): *plain_step_us receives the
+ * mean of the last 8 (0 where nothing was timed: CRONOS_NO_GRAPH, the default stream, the
+ * resident form).  *graphs receives 1 when step calls launch HIP graphs — of 2^j steps, j < 8,
+ * both buffer parities captured at creation and after cronos_set_actuation, a call's step
+ * count decomposed into powers of two from the largest down — and 0 for plain launches, which
+ * is the choice where *plain_step_us is 12 us or more (the device then trails the host; a
+ * graph launch adds tens of microseconds before its first kernel) unless CRONOS_GRAPH is set.
+ * Either way the steps' results are identical.  Either pointer may be NULL.
+ * Errors: CRONOS_EINVAL for a NULL handle. */
+cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us);
 
 /* Launch configuration chosen by the autotuner for a problem. */
 typedef struct {

@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT, VERLET, RESIDENT, WIDE_ENTRIES = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80, 0x100, 0x200)
 NO_GRID = 0x400
+GRAPH = 0x800
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -108,6 +109,7 @@ _SIGS = {
     "cronos_candidate_points": (C.c_int, [_p, _i64, _i32, _i32, C.c_uint64, _p]),
     "cronos_cutoff_springs": (C.c_int, [_i64, _p, _f64, _i64, _p, C.POINTER(_i64)]),
     "cronos_point_params": (C.c_int, [_i64, _p, _i64, _p, _f64, _f64, _f64, _i32, _f64, _p, _p, _p, _p]),
+    "cronos_launch_mode": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_f64)]),
     "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
                                        C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
@@ -328,6 +330,14 @@ def cronos_launch_config(sim: Sim) -> dict:
     _check(_lib.cronos_launch_config(sim.handle, C.byref(b), C.byref(bt), C.byref(pg), C.byref(fm), C.byref(ln)))
     return {"block_masses": b.value, "batch": bt.value, "persistent_groups": pg.value, "step_form": FORMS[fm.value],
             "lanes_per_mass": ln.value}
+
+
+def cronos_launch_mode(sim: Sim) -> dict:
+    """{"hip_graph": whether step calls launch HIP graphs, "plain_step_us": step time with
+    plain launches measured at creation}."""
+    g, t = _i32(), _f64(0.0)
+    _check(_lib.cronos_launch_mode(sim.handle, C.byref(g), C.byref(t)))
+    return {"hip_graph": bool(g.value), "plain_step_us": t.value}
 
 
 def cronos_destroy(sim: Sim):

@@ -46,7 +46,11 @@ extern "C" const char* cronos_version(void) { return "cronos-gfx950 0.1"; }
 
 namespace {
 
-constexpr int kGraphSteps = 16;  // steps per captured graph (even: ping-pong parity preserved)
+// Step graphs: for each parity of the position buffers, one HIP graph of 2^j steps for
+// j < kGraphLevels (1 .. 128 steps); a call of n steps launches n's binary decomposition from
+// the largest level down, so consecutive launches of a graph run without the ~8 us the device
+// leaves between two graphs more than once per 128 steps.
+constexpr int kGraphLevels = 8;
 constexpr int kResidentSteps = 4096;  // steps per launch of the resident form
 
 #define HIP_TRY(expr)                                                                             \
@@ -102,9 +106,10 @@ struct cronos_sim_t {
     double dt = 0.0, omega = 0.0;
     unsigned long long cycles = 0;       // frac(f dt) * 2^64: period fraction per step
     bool actuated = false, use_graph = true;
+    double plain_step_us = 0.0;          // step time with plain launches, measured at creation
     bool verlet = false;                 // integrator of eqs. (5)-(6): first step kicks dt / 2
     bool half_kick = false;              // the next step is Verlet's first
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2][kGraphLevels] = {};   // [parity][level]: 2^level steps
     std::vector<float> inv_m;            // new order
     std::vector<uint16_t> h_grp;         // per entry factor index (actuated sims), for the adjoint reduction
     std::vector<double> h_phase, h_amp;  // actuation parameters last set
@@ -126,8 +131,9 @@ void free_device(cronos_sim_t* s) {
                     d.body_out, d.fout, d.grid_halo, d.grid_org, d.grid_k};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    for (auto& g : s->graph)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& per : s->graph)
+        for (auto& g : per)
+            if (g) (void)hipGraphExecDestroy(g);
     RolloutBuffers& r = s->ro;
     if (r.bwd_graph) (void)hipGraphExecDestroy(r.bwd_graph);
     for (hipEvent_t e : r.ev)
@@ -400,25 +406,66 @@ double omega_max(const cronos::Layout& L, const cronos_desc& d, const std::vecto
     return std::sqrt(std::max(lam, 0.0));
 }
 
+// One step's launches from buffer set s->cur into the other one (s->cur is not flipped).
+cronos_status enqueue_one(cronos_sim_t* s) {
+    if (s->actuated && !cronos::fused_actuation(s->d))
+        HIP_TRY(cronos::launch_actuation(s->d, s->cycles, 1, s->stream, -1, nullptr, s->cur));
+    HIP_TRY(cronos::launch_step(s->d, s->cur, s->p, s->stream));
+    return CRONOS_OK;
+}
+
 cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
-    const bool separate = s->actuated && !cronos::fused_actuation(s->d);
     for (int64_t k = 0; k < n; ++k) {
-        if (separate) HIP_TRY(cronos::launch_actuation(s->d, s->cycles, 1, s->stream, -1, nullptr, s->cur));
-        HIP_TRY(cronos::launch_step(s->d, s->cur, s->p, s->stream));
+        TRY(enqueue_one(s));
         s->cur ^= 1;
     }
     return CRONOS_OK;
 }
 
-// Captures kGraphSteps launches starting from position buffer `par` as one HIP graph (if not
+// Graphs or plain launches for cronos_step.  A graph submits its launches for a fraction of
+// the host time that one launch per kernel costs, which is what a step shorter than that
+// host time needs; but each graph launch takes tens of microseconds before its first kernel
+// starts, and once the device is the slower side plain launches run no slower.  The step
+// time with plain launches is measured here, on the simulation's stream: the launches repeat
+// one step from the current buffers (positions, velocities, step counter) into the other set,
+// which the next real step overwrites anyway, so the state is unchanged.  Steps of at least
+// kPlainStepUs keep plain launches; CRONOS_GRAPH and CRONOS_NO_GRAPH override the choice.
+constexpr double kPlainStepUs = 12.0;
+constexpr int kModeTimedSteps = 8;
+
+cronos_status choose_launch_mode(cronos_sim_t* s, uint32_t flags) {
+    if (!s->use_graph || !s->stream || s->d.resident) return CRONOS_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CRONOS_EDEVICE, "create: hipEventCreate failed");
+    }
+    cronos_status st = enqueue_one(s);   // untimed: first launch of each kernel
+    if (st == CRONOS_OK && hipEventRecord(e0, s->stream) != hipSuccess) st = CRONOS_EDEVICE;
+    for (int k = 0; k < kModeTimedSteps && st == CRONOS_OK; ++k) st = enqueue_one(s);
+    if (st == CRONOS_OK && hipEventRecord(e1, s->stream) != hipSuccess) st = CRONOS_EDEVICE;
+    float ms = 0.0f;
+    if (st == CRONOS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = CRONOS_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == CRONOS_EDEVICE) return fail(CRONOS_EDEVICE, "create: timing the plain launches failed");
+    if (st != CRONOS_OK) return st;
+    s->plain_step_us = 1e3 * (double)ms / kModeTimedSteps;
+    if (!(flags & CRONOS_GRAPH) && s->plain_step_us >= kPlainStepUs) s->use_graph = false;
+    return CRONOS_OK;
+}
+
+// Captures 2^level launches starting from position buffer `par` as one HIP graph (if not
 // already held).  Capture only records the launches; nothing runs.
-cronos_status ensure_graph(cronos_sim_t* s, int par) {
-    if (s->graph[par]) return CRONOS_OK;
+cronos_status ensure_graph(cronos_sim_t* s, int par, int level) {
+    if (s->graph[par][level]) return CRONOS_OK;
     hipGraph_t g = nullptr;
     const int cur0 = s->cur;
     s->cur = par;
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    cronos_status st = enqueue_plain(s, kGraphSteps);
+    cronos_status st = enqueue_plain(s, (int64_t)1 << level);
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     s->cur = cur0;
     if (st != CRONOS_OK) {
@@ -426,22 +473,32 @@ cronos_status ensure_graph(cronos_sim_t* s, int par) {
         return st;
     }
     if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&s->graph[par], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->graph[par][level], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        s->graph[par] = nullptr;
+        s->graph[par][level] = nullptr;
         return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     return CRONOS_OK;
 }
 
-// Both parities' graphs, built ahead of the first cronos_step (at creation and whenever the
-// parameters they capture change), so that no step call pays for capture and instantiation.
+// Every level's graph for both parities, built ahead of the first cronos_step (at creation and
+// whenever the parameters they capture change), so that no step call pays for capture and
+// instantiation.
 cronos_status prepare_graphs(cronos_sim_t* s) {
     if (!s->use_graph || !s->stream || s->d.resident) return CRONOS_OK;
-    TRY(ensure_graph(s, 0));
-    TRY(ensure_graph(s, 1));
+    for (int par = 0; par < 2; ++par)
+        for (int level = 0; level < kGraphLevels; ++level) TRY(ensure_graph(s, par, level));
     return CRONOS_OK;
+}
+
+void drop_graphs(cronos_sim_t* s) {
+    for (auto& per : s->graph)
+        for (auto& g : per)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
 }
 
 // ---- autotuner cache: (arch, log2 N, log2 S, actuated, contact) -> launch configuration
@@ -597,6 +654,10 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     sim->dt = d->dt;
     sim->device = d->device;
     sim->use_graph = !(d->flags & CRONOS_NO_GRAPH);
+    if ((d->flags & CRONOS_NO_GRAPH) && (d->flags & CRONOS_GRAPH)) {
+        delete sim;
+        return fail(CRONOS_EINVAL, "create: CRONOS_GRAPH and CRONOS_NO_GRAPH together");
+    }
 
     // ---- host arrays in the new order
     std::vector<double> xn(3 * n), mn(n), ks(s);
@@ -1058,7 +1119,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     sim->lay.nbr_local.shrink_to_fit();
     sim->lay.entry_csr.clear();
     sim->lay.entry_csr.shrink_to_fit();
-    if ((st = prepare_graphs(sim)) != CRONOS_OK) {
+    if ((st = choose_launch_mode(sim, d->flags)) != CRONOS_OK || (st = prepare_graphs(sim)) != CRONOS_OK) {
         free_device(sim);
         delete sim;
         return st;
@@ -1097,11 +1158,7 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
     double amax = 0.0;
     for (size_t g = 0; g < m; ++g) amax = std::max(amax, std::fabs(amp[g]));
     sim->p.safe = (float)(4.0 * sim->rest_max * (1.0 + amax));
-    for (auto& gr : sim->graph)   // graphs captured the old parameters
-        if (gr) {
-            (void)hipGraphExecDestroy(gr);
-            gr = nullptr;
-        }
+    drop_graphs(sim);             // graphs captured the old parameters
     if (sim->ro.bwd_graph) {      // so did the reverse sweep's recompute (p.safe among them)
         (void)hipGraphExecDestroy(sim->ro.bwd_graph);
         sim->ro.bwd_graph = nullptr;
@@ -1142,11 +1199,14 @@ extern "C" cronos_status cronos_step(cronos_sim sim, int64_t n_steps) {
         sim->half_kick = false;
         --left;
     }
-    if (sim->use_graph && sim->stream && left >= kGraphSteps) {
-        TRY(ensure_graph(sim, sim->cur));
-        while (left >= kGraphSteps) {
-            HIP_TRY(hipGraphLaunch(sim->graph[sim->cur], sim->stream));
-            left -= kGraphSteps;
+    if (sim->use_graph && sim->stream) {
+        while (left > 0) {
+            int level = kGraphLevels - 1;
+            while (((int64_t)1 << level) > left) --level;
+            TRY(ensure_graph(sim, sim->cur, level));
+            HIP_TRY(hipGraphLaunch(sim->graph[sim->cur][level], sim->stream));
+            if (level == 0) sim->cur ^= 1;   // an odd number of steps flips the buffers
+            left -= (int64_t)1 << level;
         }
     }
     TRY(enqueue_plain(sim, left));
@@ -1754,6 +1814,13 @@ extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_mas
                      : sim->d.narrow ? CRONOS_FORM_NARROW
                      : sim->d.packed ? CRONOS_FORM_TABLE
                                      : CRONOS_FORM_EXPLICIT;
+    return CRONOS_OK;
+}
+
+extern "C" cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us) {
+    if (!sim) return fail(CRONOS_EINVAL, "launch_mode: NULL handle");
+    if (graphs) *graphs = sim->use_graph && sim->stream && !sim->d.resident ? 1 : 0;
+    if (plain_step_us) *plain_step_us = sim->plain_step_us;
     return CRONOS_OK;
 }
 
