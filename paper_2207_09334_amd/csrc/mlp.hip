@@ -62,6 +62,17 @@ struct GemmArgs {
     long ldct;
     const float* Z;       // pre-activation Z[m * ldz + n] (backward GELU)
     long ldz;
+    int nbx, nby, tiles;  // column tiles, row tiles and their product with the K-splits
+    // linear output with the loss (T non-null): dY = 2 (Y - T) / (rows n_real) as BF16, row-major
+    // dY[m * lddy + n] for n < N (zero beyond n_real and below M beyond `rows`) and transposed
+    // dYt[n * lddyt + m] for n < n_real; the sum of squares of Y - T per row tile in loss_part
+    const float* T;       // targets T[m * n_real + n], m < rows
+    bf16* dY;
+    long lddy;
+    bf16* dYt;
+    long lddyt;
+    double* loss_part;
+    int rows;
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -74,16 +85,21 @@ __device__ __forceinline__ uint32_t pack2(bf16 lo, bf16 hi) {
     return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
 }
 
+constexpr int kMaxBK = 128;
+
+// One workgroup's 64 x 64 tile (column tile bx, row tile by, K-split bz) of the product g,
+// staged through As / Bs (two buffers of 64 rows of BK + 8 elements each, at least).
 template <int EPI, int BK>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz, bf16* __restrict__ As,
+                                          bf16* __restrict__ Bs) {
     constexpr int LDK = BK + 8;               // LDS row pitch in elements (16-byte reads stay conflict-free)
     constexpr int CPR = BK / 8;               // 16-byte chunks per tile row
     constexpr int LOADS = kBM * CPR / 256;    // 16-byte loads per thread per operand per K-step
-    __shared__ __attribute__((aligned(16))) bf16 As[2][kBM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][kBN * LDK];
+    constexpr int BUF = kBM * LDK;            // elements of one buffer
+    static_assert(BK <= kMaxBK, "K-step deeper than the LDS buffers");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-    const int kbeg = blockIdx.z * g.k_chunk;
+    const int m0 = by * kBM, n0 = bx * kBN;
+    const int kbeg = bz * g.k_chunk;
     const int kend = min(g.K, kbeg + g.k_chunk);
     const int nk = (kend - kbeg) / BK;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -102,8 +118,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
             const int c = t + 256 * i, row = c / CPR, kc = (c % CPR) * 8;
-            *reinterpret_cast<uint4*>(&As[buf][row * LDK + kc]) = ra[i];
-            *reinterpret_cast<uint4*>(&Bs[buf][row * LDK + kc]) = rb[i];
+            *reinterpret_cast<uint4*>(&As[buf * BUF + row * LDK + kc]) = ra[i];
+            *reinterpret_cast<uint4*>(&Bs[buf * BUF + row * LDK + kc]) = rb[i];
         }
     };
 
@@ -113,6 +129,20 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+    // linear output with the loss: the targets this thread's outputs meet, loaded before the
+    // K-loop so that their latency hides behind it
+    float tgt[2][2][4] = {};
+    if (EPI == kLinear && g.T) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int mb = m0 + wm + i * 16 + (lane >> 4) * 4, n = n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (n < g.n_real && mb + r < g.rows) tgt[i][j][r] = g.T[(long)(mb + r) * g.n_real + n];
+            }
+    }
 
     if (nk > 0) {
         gload(kbeg);
@@ -127,10 +157,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wm + i * 16 + r16) * LDK + ks + k8]);
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur * BUF + (wm + i * 16 + r16) * LDK + ks + k8]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wn + j * 16 + r16) * LDK + ks + k8]);
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur * BUF + (wn + j * 16 + r16) * LDK + ks + k8]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -141,6 +171,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         __syncthreads();
     }
 
+    double lsum = 0.0;   // linear output with the loss: this thread's squares of Y - T
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -150,15 +181,35 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             if (n >= g.N) continue;
             if (EPI == kPartial) {
                 if (n >= g.n_real) continue;
-                float* out = g.Cf + blockIdx.z * g.part_stride;
+                float* out = g.Cf + bz * g.part_stride;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     if (mb + r < g.M) out[(long)(mb + r) * g.ldcf + n] = acc[i][j][r];
             } else if (EPI == kLinear) {
-                if (n >= g.n_real) continue;
+                if (!g.T) {
+                    if (n >= g.n_real) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (mb + r < g.M) g.Cf[(long)(mb + r) * g.ldcf + n] = acc[i][j][r] + g.bias[n];
+                    for (int r = 0; r < 4; ++r)
+                        if (mb + r < g.M) g.Cf[(long)(mb + r) * g.ldcf + n] = acc[i][j][r] + g.bias[n];
+                } else {
+                    // M is a multiple of 64 here (padded minibatch rows)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = mb + r;
+                        float d = 0.0f;
+                        if (n < g.n_real) {
+                            const float y = acc[i][j][r] + g.bias[n];
+                            g.Cf[(long)row * g.ldcf + n] = y;
+                            if (row < g.rows) {
+                                d = y - tgt[i][j][r];
+                                lsum += (double)d * (double)d;
+                            }
+                        }
+                        const bf16 v = (bf16)(2.0f * d / (float)(g.rows * g.n_real));
+                        g.dY[(long)row * g.lddy + n] = v;
+                        if (n < g.n_real) g.dYt[(long)n * g.lddyt + row] = v;
+                    }
+                }
             } else {
                 // forward / backward GELU: M is a multiple of 64 (padded minibatch rows)
                 bf16 hv[4];
@@ -179,6 +230,43 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
                     *reinterpret_cast<uint2*>(g.Ct + (long)n * g.ldct + mb) = uint2{pack2(hv[0], hv[1]), pack2(hv[2], hv[3])};
             }
         }
+    if (EPI == kLinear && g.T) {
+        // the row tile's loss partial, summed over the workgroup in a fixed order (the K-loop
+        // ended with a barrier, so As is free)
+        double* red = reinterpret_cast<double*>(As);
+        red[t] = lsum;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) g.loss_part[by] = red[0];
+    }
+}
+
+template <int EPI, int BK>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) bf16 As[2 * kBM * (BK + 8)];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2 * kBN * (BK + 8)];
+    gemm_tile<EPI, BK>(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bs);
+}
+
+// Two independent products in one launch (the backward's weight gradient of a layer and the
+// gradient into its input both read only that layer's dZ): workgroups below g1's tile count
+// take g1's tiles, the rest g2's, so both run side by side on the chip without a second
+// stream.  Tiles are numbered column fastest, then row, then split.
+template <int E1, int BK1, int E2, int BK2>
+__global__ void __launch_bounds__(256) gemm_pair_kernel(GemmArgs g1, GemmArgs g2) {
+    constexpr int BK = BK1 > BK2 ? BK1 : BK2;
+    __shared__ __attribute__((aligned(16))) bf16 As[2 * kBM * (BK + 8)];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2 * kBN * (BK + 8)];
+    int tile = blockIdx.x;
+    if (tile < g1.tiles) {
+        gemm_tile<E1, BK1>(g1, tile % g1.nbx, (tile / g1.nbx) % g1.nby, tile / (g1.nbx * g1.nby), As, Bs);
+    } else {
+        tile -= g1.tiles;
+        gemm_tile<E2, BK2>(g2, tile % g2.nbx, (tile / g2.nbx) % g2.nby, tile / (g2.nbx * g2.nby), As, Bs);
+    }
 }
 
 // Sum of `splits` FP32 partials in split order: out[i] = part[0][i] + part[1][i] + ...
@@ -188,33 +276,6 @@ __global__ void splitk_sum_kernel(const float* part, long stride, int splits, fl
     float s = part[i];
     for (int z = 1; z < splits; ++z) s += part[z * stride + i];
     out[i] = s;
-}
-
-// dY = 2 (Y - T) / (rows * n_out) as BF16, row-major [P][ldy] (zero on padding rows and
-// columns) and transposed [n_out][ldt]; per-block loss partials.
-__global__ void __launch_bounds__(256) loss_kernel(const float* Y, const float* T, bf16* dY, long ldy, bf16* dYt, long ldt,
-                                                   double* part, int rows, int padded_rows, int n_out) {
-    __shared__ double red[256];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double l = 0.0;
-    if (i < padded_rows * ldy) {
-        const int r = i / (int)ldy, c = i % (int)ldy;
-        float d = 0.0f;
-        if (r < rows && c < n_out) {
-            d = Y[r * n_out + c] - T[r * n_out + c];
-            l = (double)d * (double)d;
-        }
-        const bf16 v = (bf16)(2.0f * d / (float)(rows * n_out));
-        dY[i] = v;
-        if (c < n_out) dYt[(long)c * ldt + r] = v;
-    }
-    red[threadIdx.x] = l;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // Where each layer's weights sit in the parameter vector and in the two BF16 shadows.
@@ -337,16 +398,52 @@ struct cronos_mlp_t {
 
 namespace {
 
+// Tile counts of g over `splits` K-chunks, and the K-step it takes (128, 64 or 32: the
+// deepest that divides K and the chunk).
+int prepare(GemmArgs& g, int splits) {
+    g.nbx = (g.N + kBN - 1) / kBN;
+    g.nby = (g.M + kBM - 1) / kBM;
+    g.tiles = g.nbx * g.nby * splits;
+    if (splits == 1) g.k_chunk = g.K;
+    if (g.K % 128 == 0 && g.k_chunk % 128 == 0) return 128;
+    if (g.K % 64 == 0 && g.k_chunk % 64 == 0) return 64;
+    return 32;
+}
+
 template <int EPI>
 hipError_t gemm(hipStream_t st, GemmArgs g, int splits = 1) {
-    dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, splits);
-    if (splits == 1) g.k_chunk = g.K;
-    if (g.K % 128 == 0 && g.k_chunk % 128 == 0)
+    const int bk = prepare(g, splits);
+    const dim3 grid(g.nbx, g.nby, splits);
+    if (bk == 128)
         hipLaunchKernelGGL((gemm_kernel<EPI, 128>), grid, dim3(256), 0, st, g);
-    else if (g.K % 64 == 0 && g.k_chunk % 64 == 0)
+    else if (bk == 64)
         hipLaunchKernelGGL((gemm_kernel<EPI, 64>), grid, dim3(256), 0, st, g);
     else
         hipLaunchKernelGGL((gemm_kernel<EPI, 32>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+template <int E1, int BK1, int E2>
+void launch_pair2(hipStream_t st, const GemmArgs& g1, const GemmArgs& g2, int bk2) {
+    const dim3 grid((unsigned)(g1.tiles + g2.tiles));
+    if (bk2 == 128)
+        hipLaunchKernelGGL((gemm_pair_kernel<E1, BK1, E2, 128>), grid, dim3(256), 0, st, g1, g2);
+    else if (bk2 == 64)
+        hipLaunchKernelGGL((gemm_pair_kernel<E1, BK1, E2, 64>), grid, dim3(256), 0, st, g1, g2);
+    else
+        hipLaunchKernelGGL((gemm_pair_kernel<E1, BK1, E2, 32>), grid, dim3(256), 0, st, g1, g2);
+}
+
+// g1 over splits1 K-chunks and g2 (one chunk) in one launch.
+template <int E1, int E2>
+hipError_t gemm_pair(hipStream_t st, GemmArgs g1, int splits1, GemmArgs g2) {
+    const int bk1 = prepare(g1, splits1), bk2 = prepare(g2, 1);
+    if (bk1 == 128)
+        launch_pair2<E1, 128, E2>(st, g1, g2, bk2);
+    else if (bk1 == 64)
+        launch_pair2<E1, 64, E2>(st, g1, g2, bk2);
+    else
+        launch_pair2<E1, 32, E2>(st, g1, g2, bk2);
     return hipGetLastError();
 }
 
@@ -369,8 +466,9 @@ void free_mlp(cronos_mlp_t* q) {
     if (q->own_stream && q->stream) (void)hipStreamDestroy(q->stream);
 }
 
-// Forward over `rows` (<= max_rows, padded to 64) rows already in q->x.
-cronos_status forward_dev(cronos_mlp_t* q, int rows) {
+// Forward over `rows` (<= max_rows, padded to 64) rows already in q->x; with_loss: the output
+// product's epilogue also forms the loss partials and dY from the targets in q->t.
+cronos_status forward_dev(cronos_mlp_t* q, int rows, bool with_loss) {
     const int P = (rows + 63) / 64 * 64;
     const long R = q->max_rows;
     const bf16* in = q->x;
@@ -406,6 +504,15 @@ cronos_status forward_dev(cronos_mlp_t* q, int rows) {
     g.bias = q->p + q->off_b[3];
     g.Cf = q->y;
     g.ldcf = q->sizes[4];
+    if (with_loss) {
+        g.T = q->t;
+        g.dY = q->dy;
+        g.lddy = q->wp[4];
+        g.dYt = q->dyt;
+        g.lddyt = R;
+        g.loss_part = q->part;
+        g.rows = rows;
+    }
     HIP_TRY(gemm<kLinear>(q->stream, g));
     return CRONOS_OK;
 }
@@ -416,11 +523,6 @@ cronos_status forward_dev(cronos_mlp_t* q, int rows) {
 cronos_status backward_dev(cronos_mlp_t* q, int rows, bool sum_grads) {
     const int P = (rows + 63) / 64 * 64;
     const long R = q->max_rows;
-    const int n_out = q->sizes[4];
-    const int nel = P * q->wp[4];
-    hipLaunchKernelGGL(loss_kernel, dim3((nel + 255) / 256), dim3(256), 0, q->stream, q->y, q->t, q->dy, (long)q->wp[4],
-                       q->dyt, R, q->part, rows, P, n_out);
-    HIP_TRY(hipGetLastError());
     const int splits = (P + kSplitRows - 1) / kSplitRows;
     const bf16* dnext = q->dy;     // [P][wp[l+1]]
     const bf16* dnext_t = q->dyt;  // [sizes[l+1]][R]
@@ -440,12 +542,11 @@ cronos_status backward_dev(cronos_mlp_t* q, int rows, bool sum_grads) {
         g.ldcf = N;
         if (splits == 1) {
             g.Cf = q->grad + q->off_w[l];
-            HIP_TRY(gemm<kPartial>(q->stream, g, 1));
         } else {
             g.Cf = q->part_w + q->off_w[l];
             g.part_stride = q->n_params;
-            HIP_TRY(gemm<kPartial>(q->stream, g, splits));
         }
+        if (l == 0) HIP_TRY(gemm<kPartial>(q->stream, g, splits));
         if (l) {
             // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1}) : (P x wp[l+1]) (wp[l+1] x wp[l])
             GemmArgs d{};
@@ -463,7 +564,8 @@ cronos_status backward_dev(cronos_mlp_t* q, int rows, bool sum_grads) {
             d.ldct = R;
             d.Z = q->z[l - 1];
             d.ldz = q->wp[l];
-            HIP_TRY(gemm<kBwdGelu>(q->stream, d));
+            // both read dZ_l only: one launch for the pair
+            HIP_TRY((gemm_pair<kPartial, kBwdGelu>(q->stream, g, splits, d)));
             dnext = q->dz[l - 1];
             dnext_t = q->dzt[l - 1];
         }
@@ -507,8 +609,7 @@ cronos_status adam_dev(cronos_mlp_t* q, double lr, double b1, double b2, double 
 }
 
 double loss_from_parts(cronos_mlp_t* q, int rows, cronos_status* st) {
-    const int P = (rows + 63) / 64 * 64;
-    const int nb = (P * q->wp[4] + 255) / 256;
+    const int nb = (rows + 63) / 64;   // one partial per 64-row tile of the output product
     std::vector<double> h(nb);
     *st = CRONOS_OK;
     if (hipMemcpyAsync(h.data(), q->part, nb * sizeof(double), hipMemcpyDeviceToHost, q->stream) != hipSuccess ||
@@ -651,7 +752,7 @@ extern "C" cronos_status cronos_mlp_forward(cronos_mlp q, const float* x, int64_
         const int r = (int)std::min<int64_t>(q->max_rows, rows - r0);
         cronos_status st = upload_rows(q, x + r0 * q->sizes[0], nullptr, r);
         if (st != CRONOS_OK) return st;
-        st = forward_dev(q, r);
+        st = forward_dev(q, r, false);
         if (st != CRONOS_OK) return st;
         HIP_TRY(hipMemcpyAsync(y + r0 * n_out, q->y, (size_t)r * n_out * sizeof(float), hipMemcpyDeviceToHost, q->stream));
         HIP_TRY(hipStreamSynchronize(q->stream));
@@ -665,7 +766,7 @@ extern "C" cronos_status cronos_mlp_loss_grad(cronos_mlp q, const float* x, cons
     if (!q || !x || !t || rows < 1 || rows > q->max_rows) return fail(CRONOS_EINVAL, "mlp_loss_grad: bad arguments");
     HIP_TRY(hipSetDevice(q->device));
     cronos_status st = upload_rows(q, x, t, rows);
-    if (st == CRONOS_OK) st = forward_dev(q, rows);
+    if (st == CRONOS_OK) st = forward_dev(q, rows, true);
     if (st == CRONOS_OK) st = backward_dev(q, rows, true);
     if (st != CRONOS_OK) return st;
     const double l = loss_from_parts(q, rows, &st);
@@ -730,7 +831,7 @@ extern "C" cronos_status cronos_mlp_train(cronos_mlp q, const float* x, const fl
         for (int64_t b0 = 0; b0 < rows; b0 += batch) {
             const int r = (int)std::min<int64_t>(batch, rows - b0);
             cronos_status st = gather_rows(q, q->data_x, q->data_t, q->idx + b0, r);
-            if (st == CRONOS_OK) st = forward_dev(q, r);
+            if (st == CRONOS_OK) st = forward_dev(q, r, true);
             if (st == CRONOS_OK) st = backward_dev(q, r, false);
             const double lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * (double)step++ / (double)last));
             if (st == CRONOS_OK) st = adam_dev(q, lr_t, 0.9, 0.999, 1e-8);
