@@ -76,6 +76,8 @@ struct DeviceArrays {
     int32_t* grid_halo = nullptr;        // [nblk][488] new index of each halo cell of the block's tile, -1 outside
     int4* grid_org = nullptr;            // [nblk] grid coordinates of the block's first node
     float* grid_k = nullptr;             // [27][26] k per (boundary class, direction)
+    uint32_t* grid_tab = nullptr;        // [512] lane's tile cell | lx << 10 | ly << 13 | lz << 16, then
+                                         // [488] tile cell of each halo slot
     float grid_kin[3] = {};              // interior k per direction kind (1, 2, 3 non-zero offsets)
     float grid_l0[3] = {};               // rest length per direction kind
 };

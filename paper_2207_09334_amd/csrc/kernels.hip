@@ -1214,36 +1214,14 @@ struct GridArgs {
     const int32_t* __restrict__ halo;   // [nblk][kGridHalo] new index of each halo cell, -1 outside
     const int4* __restrict__ org;       // [nblk] grid coordinates of the block's first node
     const float* __restrict__ kcls;     // [27][26] k per (boundary class, direction)
+    const uint32_t* __restrict__ tab;   // [512] lane's tile cell | lx << 10 | ly << 13 | lz << 16,
+                                        // then [488] tile cell of each halo slot
     int nblk, nx, ny, nz;
     // per direction kind (edge, face diagonal, body diagonal: 1, 2 or 3 non-zero offsets)
     float kin[3];                       // k of interior masses (class 13)
     float l0[3];                        // rest length
     double q[3];                        // its square, exact in FP64
 };
-
-// Tile cell of halo slot h: the z = 0 face, the z = 9 face, then for z = 1..8 the y = 0 row,
-// the y = 9 row and the x = 0 / x = 9 ends of rows y = 1..8 (100 + 100 + 8 x 36 = 488).
-__device__ __forceinline__ int grid_halo_cell(int h) {
-    int x, y, z;
-    if (h < 200) {
-        z = h < 100 ? 0 : 9;
-        const int r = h < 100 ? h : h - 100;
-        y = r / 10;
-        x = r - 10 * y;
-    } else {
-        const int r = h - 200;
-        z = 1 + r / 36;
-        const int s = r - 36 * (z - 1);
-        if (s < 20) {
-            y = s < 10 ? 0 : 9;
-            x = s < 10 ? s : s - 10;
-        } else {
-            y = 1 + ((s - 20) >> 1);
-            x = ((s - 20) & 1) * 9;
-        }
-    }
-    return (z * kGridPitch + y) * kGridPitch + x;
-}
 
 // Sum of the 26 spring forces of the lane's mass at tile cell `cell`.  INTERIOR: every mass of
 // the wavefront is interior, so each direction's k is the same for all lanes.
@@ -1274,22 +1252,27 @@ __global__ void __launch_bounds__(kGridThreads) step_grid_kernel(GridArgs a, Ste
     if (b >= a.nblk) return;
     const int t = threadIdx.x;
     const int i = b * kGridThreads + t;
-    // Morton-local index t: x from bits 0, 3, 6; y from 1, 4, 7; z from 2, 5, 8
-    const int lx = (t & 1) | ((t >> 2) & 2) | ((t >> 4) & 4);
-    const int ly = ((t >> 1) & 1) | ((t >> 3) & 2) | ((t >> 5) & 4);
-    const int lz = ((t >> 2) & 1) | ((t >> 4) & 2) | ((t >> 6) & 4);
-    const int cell = ((lz + 1) * kGridPitch + (ly + 1)) * kGridPitch + (lx + 1);
+    const uint32_t lane_info = a.tab[t];      // the block's mass t: its tile cell and local x, y, z
+    const int cell = (int)(lane_info & 1023u);
     const float4 xi = a.xin[i];
     tile[cell] = xi;
     for (int h = t; h < kGridHalo; h += kGridThreads) {
         const int g = a.halo[(long)b * kGridHalo + h];
-        tile[grid_halo_cell(h)] = g >= 0 ? a.xin[g] : make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+        tile[a.tab[kGridThreads + h]] = g >= 0 ? a.xin[g] : make_float4(1e18f, 1e18f, 1e18f, 0.0f);
     }
-    for (int q = t; q < 27 * 26; q += kGridThreads) kcls[q] = a.kcls[q];
+    // a block that touches no face of the box holds only interior masses (class 13): it needs
+    // neither the class of each mass nor the per-class k table
     const int4 o = a.org[b];
-    const int gx = o.x + lx, gy = o.y + ly, gz = o.z + lz;
-    const int cls = (gx == 0 ? 0 : gx == a.nx - 1 ? 2 : 1) + 3 * (gy == 0 ? 0 : gy == a.ny - 1 ? 2 : 1) +
-                    9 * (gz == 0 ? 0 : gz == a.nz - 1 ? 2 : 1);
+    const bool face = o.x == 0 || o.y == 0 || o.z == 0 || o.x + kGridEdge >= a.nx || o.y + kGridEdge >= a.ny ||
+                      o.z + kGridEdge >= a.nz;
+    int cls = 13;
+    if (face) {
+        for (int q = t; q < 27 * 26; q += kGridThreads) kcls[q] = a.kcls[q];
+        const int gx = o.x + (int)((lane_info >> 10) & 7u), gy = o.y + (int)((lane_info >> 13) & 7u),
+                  gz = o.z + (int)((lane_info >> 16) & 7u);
+        cls = (gx == 0 ? 0 : gx == a.nx - 1 ? 2 : 1) + 3 * (gy == 0 ? 0 : gy == a.ny - 1 ? 2 : 1) +
+              9 * (gz == 0 ? 0 : gz == a.nz - 1 ? 2 : 1);
+    }
     __syncthreads();
     const float* kc = kcls + 26 * cls;
     const bool interior = __builtin_amdgcn_ballot_w64(cls != 13) == 0;
@@ -1299,9 +1282,11 @@ __global__ void __launch_bounds__(kGridThreads) step_grid_kernel(GridArgs a, Ste
         if (interior) gather_grid<kPlain, true>(tile, kc, cell, xi, a, fx, fy, fz);
         else gather_grid<kPlain, false>(tile, kc, cell, xi, a, fx, fy, fz);
     } else if (mode == kExactZ) {
-        gather_grid<kExactZ, false>(tile, kc, cell, xi, a, fx, fy, fz);
+        if (interior) gather_grid<kExactZ, true>(tile, kc, cell, xi, a, fx, fy, fz);
+        else gather_grid<kExactZ, false>(tile, kc, cell, xi, a, fx, fy, fz);
     } else {
-        gather_grid<kExactAll, false>(tile, kc, cell, xi, a, fx, fy, fz);
+        if (interior) gather_grid<kExactAll, true>(tile, kc, cell, xi, a, fx, fy, fz);
+        else gather_grid<kExactAll, false>(tile, kc, cell, xi, a, fx, fy, fz);
     }
     float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
     float4 xo;
@@ -1359,7 +1344,7 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
                           int cur) {
     if (d.grid) {
         if (fuse) return hipErrorInvalidValue;
-        GridArgs g{xin, vin, xout, vout, vstar, d.fext, d.grid_halo, d.grid_org, d.grid_k, (int)d.nblk,
+        GridArgs g{xin, vin, xout, vout, vstar, d.fext, d.grid_halo, d.grid_org, d.grid_k, d.grid_tab, (int)d.nblk,
                    d.grid_dim[0], d.grid_dim[1], d.grid_dim[2], {}, {}, {}};
         for (int q = 0; q < 3; ++q) {
             g.kin[q] = d.grid_kin[q];

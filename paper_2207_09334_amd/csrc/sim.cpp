@@ -128,7 +128,7 @@ void free_device(cronos_sim_t* s) {
     cronos::DeviceArrays& d = s->d;
     void* ptrs[] = {d.narrow, d.packed, d.table, d.blk_groups, d.sp_rec, d.sp_grp, d.sp_ptr, d.x[0], d.x[1], d.v[0], d.v[1], d.mass, d.fext, d.lane_mass, d.slice_ptr, d.nbr, d.kl, d.grp, d.halo_ptr,
                     d.halo_idx, d.phase, d.amp, d.factor, d.step_ctr, d.chunks, d.body_chunk, d.chunk_part,
-                    d.body_out, d.fout, d.grid_halo, d.grid_org, d.grid_k};
+                    d.body_out, d.fout, d.grid_halo, d.grid_org, d.grid_k, d.grid_tab};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& per : s->graph)
@@ -174,6 +174,7 @@ struct GridHost {
     std::vector<int32_t> halo;   // [nblk][488]
     std::vector<int4> org;       // [nblk]
     std::vector<float> kcls;     // [27][26]
+    std::vector<uint32_t> tab;   // [512] lane: tile cell | lx << 10 | ly << 13 | lz << 16; [488] halo slot's cell
     float kin[3] = {}, l0[3] = {};   // per direction kind: 1, 2 or 3 non-zero offsets
 };
 
@@ -289,7 +290,27 @@ bool detect_grid(const cronos_desc& d, const cronos::Layout& L, GridHost& G) {
                     return false;
                 }
             }
-    // halo cells of every block's 10 x 10 x 10 tile, in the device's enumeration
+    // the kernel's per-lane and per-halo-slot tile cells: lane t holds the block's mass t,
+    // whose local coordinates are the de-interleaved bits of t (x from bits 0, 3, 6; y from
+    // 1, 4, 7; z from 2, 5, 8); halo slots in the order of the halo lists below
+    auto cell_at = [](int cx, int cy, int cz) { return (uint32_t)((cz * 10 + cy) * 10 + cx); };
+    G.tab.clear();
+    for (int t = 0; t < 512; ++t) {
+        const int lx = (t & 1) | ((t >> 2) & 2) | ((t >> 4) & 4);
+        const int ly = ((t >> 1) & 1) | ((t >> 3) & 2) | ((t >> 5) & 4);
+        const int lz = ((t >> 2) & 1) | ((t >> 4) & 2) | ((t >> 6) & 4);
+        G.tab.push_back(cell_at(lx + 1, ly + 1, lz + 1) | (uint32_t)lx << 10 | (uint32_t)ly << 13 | (uint32_t)lz << 16);
+    }
+    for (int cz : {0, 9})
+        for (int cy = 0; cy < 10; ++cy)
+            for (int cx = 0; cx < 10; ++cx) G.tab.push_back(cell_at(cx, cy, cz));
+    for (int cz = 1; cz <= 8; ++cz) {
+        for (int cy : {0, 9})
+            for (int cx = 0; cx < 10; ++cx) G.tab.push_back(cell_at(cx, cy, cz));
+        for (int cy = 1; cy <= 8; ++cy)
+            for (int cx : {0, 9}) G.tab.push_back(cell_at(cx, cy, cz));
+    }
+    // halo cells of every block's 10 x 10 x 10 tile, in the same enumeration
     G.halo.assign((size_t)nblk * 488, -1);
     cronos::parallel_for(nblk, [&](int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
@@ -1067,6 +1088,7 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             TRY(upload(&D.grid_halo, gridh.halo.data(), gridh.halo.size()));
             TRY(upload(&D.grid_org, gridh.org.data(), gridh.org.size()));
             TRY(upload(&D.grid_k, gridh.kcls.data(), gridh.kcls.size()));
+            TRY(upload(&D.grid_tab, gridh.tab.data(), gridh.tab.size()));
             for (int c = 0; c < 3; ++c) D.grid_dim[c] = gridh.dim[c];
             for (int q = 0; q < 3; ++q) {
                 D.grid_kin[q] = gridh.kin[q];
