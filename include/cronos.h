@@ -229,7 +229,10 @@ typedef struct {
     int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = the
                                      tuned value for this problem class if one is cached (see
                                      cronos_autotune), else 512 for a passive system of at least
-                                     131,072 masses and 256 otherwise                         */
+                                     131,072 masses, 64 (below 32,768 masses) or 128 for a
+                                     system under 131,072 masses whose lanes_per_mass is 0 too
+                                     (with 4 lanes per mass; not with CRONOS_NO_TABLE,
+                                     CRONOS_SPLIT or CRONOS_RESIDENT), and 256 otherwise       */
     int32_t batch;                /* incidence entries each lane keeps in flight: 2, 4 or 8;
                                      0 = tuned or 4                                           */
     int32_t persistent;           /* 1 = one persistent launch per step (a resident grid walks
@@ -238,7 +241,9 @@ typedef struct {
     int32_t lanes_per_mass;       /* lanes sharing each mass's incidence list: 1, 2 or 4
                                      (workgroups of block_masses * lanes threads, at most 1024;
                                      compact table forms with one workgroup per block only,
-                                     else 1); 0 = tuned or 1.  More than one lane per mass
+                                     else 1); 0 = tuned, or 4 for a system under 131,072
+                                     masses when block_masses is 0 (see there), or 1.  More
+                                     than one lane per mass
                                      groups each mass's force sum differently (equal to
                                      rounding, not bitwise, to one lane).  A tuned value is
                                      taken only when block_masses is 0 as well               */

@@ -632,6 +632,16 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
             if (persistent == 0) persistent = t.persistent;
         }
     }
+    // untuned default for a system too small to fill the chip with one lane per mass: 4 lanes
+    // and small workgroups (the autotuner's choice on the quadruped, cubes and beams of 13k to
+    // 64k masses and populations of 38k and 97k masses: 12-28% faster than 256-mass workgroups
+    // with one lane; at 320k and 446k masses it keeps one lane)
+    constexpr int64_t kSmallSystem = 131072;
+    const uint32_t no_lanes = CRONOS_NO_TABLE | CRONOS_SPLIT | CRONOS_RESIDENT;
+    if (block == 0 && lanes == 0 && n < kSmallSystem && !(d->flags & no_lanes)) {
+        lanes = 4;
+        block = n < 32768 ? 64 : 128;
+    }
     if (batch == 0) batch = 4;
     if (persistent < 0) persistent = 0;
     if (lanes < 1) lanes = 1;

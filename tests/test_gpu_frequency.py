@@ -18,7 +18,11 @@ pytestmark = pytest.mark.gpu
 
 def test_simulated_first_frequency_matches_eigen_prediction():
     """A 61x7x5 cantilever (its first mode, bending in the thinner direction, is simple, so the
-    start shape is unique up to sign) started along that mode at 2e-4 m."""
+    start shape is unique up to sign) started along that mode at 2e-4 m.  The motion is
+    tracked by its modal coordinate, the mass-weighted projection of the displacement on the
+    mode: the other modes are M-orthogonal to it, so the high-frequency motion that the FP32
+    state's rounding feeds over 56k steps (about 1e-6 m at a single node, enough to put
+    spurious zero crossings into one node's trace) drops out."""
     w = W.cantilever(61, 7, 5)
     lat = L.build(w)
     om, modes = LN.natural_frequencies(lat.x, lat.ends, lat.k, lat.rest, lat.mass, lat.pinned, 1)
@@ -27,8 +31,8 @@ def test_simulated_first_frequency_matches_eigen_prediction():
     mode = modes[0] / np.abs(modes[0]).max()
     x0 = lat.x + 2.0e-4 * mode
     sim, nlat, _ = PR.create(w, x0=x0, gravity=(0.0, 0.0, 0.0))
-    tip = int(np.argmax(np.abs(mode).sum(axis=1)))
-    axis = int(np.argmax(np.abs(mode[tip])))
+    wm = lat.mass[:, None] * mode
+    norm = float((wm * mode).sum())
     period_steps = 2 * math.pi / w_d / dt
     every = 16
     n = int(3.3 * period_steps / every)
@@ -36,7 +40,7 @@ def test_simulated_first_frequency_matches_eigen_prediction():
     for q in range(n):
         CR.cronos_step(sim, every)
         xg, _, _ = CR.cronos_read_state(sim)
-        trace[q] = xg[tip, axis] - lat.x[tip, axis]
+        trace[q] = float((wm * (xg - lat.x)).sum()) / norm
     s = np.sign(trace)
     idx = np.nonzero(s[:-1] * s[1:] < 0)[0]
     cross = idx + trace[idx] / (trace[idx] - trace[idx + 1])

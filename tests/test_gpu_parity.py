@@ -498,14 +498,15 @@ def test_layout_of_created_sim_matches_oracle():
 
 def test_resident_form_bitwise_equal_to_table_form():
     """A system of <= 1024 masses in one workgroup, many steps per launch: bitwise the same
-    states as the per-step launches (the same gather and update; factors by the same formula),
-    for the cube drop (contact, damping) and a small actuated robot, with both integrators."""
+    states as the per-step launches with one lane per mass (the same gather and update; factors
+    by the same formula), for the cube drop (contact, damping) and a small actuated robot, with
+    both integrators."""
     cube = W.cube_drop()
     robot = W.population(1, lo=400, hi=900, first_robot=5)
     say("case: resident form vs per-step launches: cube drop 1200 steps, one robot 700 steps")
     for w, steps in ((cube, 1200), (robot, 700)):
         for integ in (0, CR.VERLET):
-            ref, _, _ = PR.create(w, flags=integ)
+            ref, _, _ = PR.create(w, flags=integ, lanes_per_mass=1)
             res, _, _ = PR.create(w, flags=integ | CR.RESIDENT)
             assert CR.cronos_launch_config(res)["step_form"] == "resident"
             assert CR.cronos_launch_config(ref)["step_form"] in ("table", "narrow")
@@ -552,7 +553,7 @@ def test_resident_form_entries_beyond_lds_bitwise_equal():
     assert degree.max() >= 40
     kw = dict(mass=np.full(len(pts), 0.1), ends=ends, k=np.full(len(ends), 1.0e4), rest=rest,
               pinned=(pts[:, 0] < pw.pin_x).astype(np.uint8), gravity=(0.0, 0.0, -9.81), damping=0.001, dt=1.0e-4)
-    ref = CR.cronos_create(pts, **kw)
+    ref = CR.cronos_create(pts, lanes_per_mass=1, **kw)
     res = CR.cronos_create(pts, flags=CR.RESIDENT, **kw)
     assert CR.cronos_launch_config(res)["step_form"] == "resident"
     assert CR.cronos_launch_config(ref)["step_form"] in ("table", "narrow")
