@@ -154,7 +154,7 @@ struct ModesBuffers {
     double* alpha = nullptr;             // [max_iter] diagonal of the tridiagonal matrix
     double* beta = nullptr;              // [max_iter] off-diagonal (beta[k] follows step k)
 };
-// Random start vector q_0 (normalised, in q[1]; q[0] must hold zeros) and M^-1/2.
+// Random start vector q_0 (normalised, in q[1]; q[0] cleared to zeros) and M^-1/2.
 hipError_t launch_modes_init(const DeviceArrays& d, int cur, ModesBuffers& m, unsigned long long seed, hipStream_t st);
 // Lanczos step k: alpha[k], beta[k] and q_{k+1} from q_k and q_{k-1}.
 hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepParams& p, ModesBuffers& m, int k,

@@ -66,10 +66,13 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
-// M^-1/2 per mass and a random start vector (zero on fixed masses); partial squared norms.
+// M^-1/2 per mass and a random start vector (zero on fixed masses); partial squared norms;
+// zeros in q_prev (the Lanczos vector before the first, cleared here by a kernel rather than a
+// memset node so that the sequence stays a plain kernel chain).
 __global__ void __launch_bounds__(256) modes_init_kernel(const float4* __restrict__ x, const float* __restrict__ mass,
                                                          double* __restrict__ ism, double* __restrict__ w,
-                                                         double* __restrict__ part, int n, unsigned long long seed) {
+                                                         double* __restrict__ q_prev, double* __restrict__ part, int n,
+                                                         unsigned long long seed) {
     __shared__ double red[kMaxWaves + 1];
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     double nn = 0.0;
@@ -80,6 +83,7 @@ __global__ void __launch_bounds__(256) modes_init_kernel(const float4* __restric
             const unsigned long long h = mix64(seed + 0x9e3779b97f4a7c15ull * (unsigned long long)(3 * (long long)i + c + 1));
             const double u = free_mass ? (double)(h >> 11) * 0x1.0p-53 - 0.5 : 0.0;
             w[3 * i + c] = u;
+            q_prev[3 * i + c] = 0.0;
             nn += u * u;
         }
     }
@@ -267,8 +271,8 @@ __global__ void __launch_bounds__(256) modes_scale_kernel(const double* __restri
 
 hipError_t launch_modes_init(const DeviceArrays& d, int cur, ModesBuffers& m, unsigned long long seed, hipStream_t st) {
     const int n = (int)d.n, g = (n + 255) / 256;
-    hipLaunchKernelGGL(modes_init_kernel, dim3(g), dim3(256), 0, st, d.x[cur], d.mass, m.ism, m.q[1], m.part_u, n,
-                       seed);
+    hipLaunchKernelGGL(modes_init_kernel, dim3(g), dim3(256), 0, st, d.x[cur], d.mass, m.ism, m.q[1], m.q[0], m.part_u,
+                       n, seed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(modes_scale_kernel, dim3(g), dim3(256), 0, st, m.part_u, g, m.q[1], m.beta, -1, n);

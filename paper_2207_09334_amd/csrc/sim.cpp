@@ -1395,7 +1395,6 @@ cronos_status check_modes_args(cronos_sim sim, int32_t n_modes, int32_t max_iter
 cronos_status lanczos_frequencies(cronos_sim sim, cronos::ModesBuffers& m, int32_t n_modes, int32_t max_iter, double tol,
                                   uint64_t seed, double* omega, int32_t* n_found, int32_t* iterations) {
     const int64_t n = sim->d.n;
-    HIP_TRY(hipMemsetAsync(m.q[0], 0, 3 * n * sizeof(double), sim->stream));
     if (sim->actuated) HIP_TRY(cronos::launch_actuation(sim->d, sim->cycles, 0, sim->stream, -1, nullptr, sim->cur));
     HIP_TRY(cronos::launch_modes_init(sim->d, sim->cur, m, seed, sim->stream));
     std::vector<double> ha(max_iter), hb(max_iter);
