@@ -562,15 +562,32 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
         }
     }
     const int i = base + own;
-    if (i >= a.n) return;
-    float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
     float4 xo;
-    integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
-              a.vstar_out ? a.vstar_out + 3 * i : nullptr);
-    a.xout[i] = xo;
-    a.vout[3 * i + 0] = vx;
-    a.vout[3 * i + 1] = vy;
-    a.vout[3 * i + 2] = vz;
+    if (i < a.n) {
+        vx = a.vin[3 * i + 0];
+        vy = a.vin[3 * i + 1];
+        vz = a.vin[3 * i + 2];
+        integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+                  a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+    }
+    // The lane->mass map scatters a wavefront's masses over the block, and scattered 16- and
+    // 12-byte stores reach HBM as partly written lines: the new state goes through LDS (the
+    // staged positions and tables are no longer read) and out in mass order, one contiguous
+    // run per array.  The launch provides at least 28 bytes of LDS per mass for it.
+    __syncthreads();
+    float4* ox = sx;
+    float* ov = reinterpret_cast<float*>(sx + a.block);
+    if (i < a.n) {
+        ox[own] = xo;
+        ov[3 * own + 0] = vx;
+        ov[3 * own + 1] = vy;
+        ov[3 * own + 2] = vz;
+    }
+    __syncthreads();
+    const int cnt = min(a.block, a.n - base);
+    for (int q = threadIdx.x; q < cnt; q += a.block) a.xout[base + q] = ox[q];
+    for (int q = threadIdx.x; q < 3 * cnt; q += a.block) a.vout[3 * (long)base + q] = ov[q];
 }
 
 // A fused-actuation launch hands the next one its step index through the other slot of the
@@ -1337,6 +1354,12 @@ size_t step_lds_bytes(const DeviceArrays& d) {
     return b;
 }
 
+// Dynamic LDS of a one-lane step launch: the staging above, and room for the new state of the
+// block's masses (a float4 and three floats each) that step_block writes out through LDS.
+size_t step_launch_lds_bytes(const DeviceArrays& d) {
+    return std::max(step_lds_bytes(d), (size_t)d.block * (sizeof(float4) + 3 * sizeof(float)));
+}
+
 bool fused_actuation(const DeviceArrays& d) { return d.grp != nullptr && (d.sp_rec || d.narrow || d.packed); }
 
 hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float* vin, float4* xout, float* vout,
@@ -1380,9 +1403,10 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
     }
     const bool persistent = d.persistent_groups > 0;
     const dim3 grid(persistent ? (unsigned)d.persistent_groups : (unsigned)grid_for(d.nblk));
+    const size_t lds1 = step_launch_lds_bytes(d);
     auto go = [&](auto normal, auto pers) {
-        if (persistent) hipLaunchKernelGGL(pers, grid, dim3(d.block), lds, st, a, p);
-        else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds, st, a, p);
+        if (persistent) hipLaunchKernelGGL(pers, grid, dim3(d.block), lds1, st, a, p);
+        else hipLaunchKernelGGL(normal, grid, dim3(d.block), lds1, st, a, p);
     };
 #define CRONOS_GO(A, E, B, M) go(step_kernel<A, E, B, M>, step_persistent<A, E, B, M>)
 // (16-bit entries exist for passive simulations only: the actuated expansion maps them to kTable,
@@ -1441,7 +1465,7 @@ hipError_t persistent_grid(const DeviceArrays& d, int exact, int* grid) {
     else
         k = d.grp ? (exact ? (const void*)step_persistent<true, true, 4, kTable> : (const void*)step_persistent<true, false, 4, kTable>)
                   : (exact ? (const void*)step_persistent<false, true, 4, kTable> : (const void*)step_persistent<false, false, 4, kTable>);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, step_lds_bytes(d));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, d.block, step_launch_lds_bytes(d));
     if (e != hipSuccess) return e;
     int g = std::max(1, per_cu) * cus;
     g = (g + 7) / 8 * 8;
