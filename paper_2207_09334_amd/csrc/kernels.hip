@@ -526,6 +526,14 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
             }
         }
     }
+    // velocities read in mass order (one contiguous run), handed to each mass's lane through LDS below
+    float vt0 = 0.0f, vt1 = 0.0f, vt2 = 0.0f;
+    if (base + (int)threadIdx.x < a.n) {
+        const long q = 3 * (long)(base + (int)threadIdx.x);
+        vt0 = a.vin[q + 0];
+        vt1 = a.vin[q + 1];
+        vt2 = a.vin[q + 2];
+    }
     const int own = stage_positions(sx, a.xin, a.halo_ptr, a.halo_idx, a.lane_mass, b, base, a.n, a.block);
     const float4 xi = sx[own];
     float fx, fy, fz;
@@ -562,22 +570,28 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
         }
     }
     const int i = base + own;
-    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
-    float4 xo;
-    if (i < a.n) {
-        vx = a.vin[3 * i + 0];
-        vy = a.vin[3 * i + 1];
-        vz = a.vin[3 * i + 2];
-        integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
-                  a.vstar_out ? a.vstar_out + 3 * i : nullptr);
-    }
     // The lane->mass map scatters a wavefront's masses over the block, and scattered 16- and
-    // 12-byte stores reach HBM as partly written lines: the new state goes through LDS (the
-    // staged positions and tables are no longer read) and out in mass order, one contiguous
-    // run per array.  The launch provides at least 28 bytes of LDS per mass for it.
+    // 12-byte accesses reach HBM as partly used lines: velocities come in (loaded above in
+    // mass order) and the new state goes out through LDS (the staged positions and tables
+    // are no longer read), one contiguous run per array.  The launch provides 40 bytes of LDS
+    // per mass for it.
     __syncthreads();
     float4* ox = sx;
     float* ov = reinterpret_cast<float*>(sx + a.block);
+    float* ovin = ov + 3 * a.block;
+    ovin[3 * threadIdx.x + 0] = vt0;
+    ovin[3 * threadIdx.x + 1] = vt1;
+    ovin[3 * threadIdx.x + 2] = vt2;
+    __syncthreads();
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    float4 xo;
+    if (i < a.n) {
+        vx = ovin[3 * own + 0];
+        vy = ovin[3 * own + 1];
+        vz = ovin[3 * own + 2];
+        integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+                  a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+    }
     if (i < a.n) {
         ox[own] = xo;
         ov[3 * own + 0] = vx;
@@ -1354,10 +1368,12 @@ size_t step_lds_bytes(const DeviceArrays& d) {
     return b;
 }
 
-// Dynamic LDS of a one-lane step launch: the staging above, and room for the new state of the
-// block's masses (a float4 and three floats each) that step_block writes out through LDS.
+// Dynamic LDS of a one-lane step launch: the staging above, and room for the old velocities
+// and the new state of the block's masses (a float4 and six floats each) that step_block
+// passes through LDS in mass order.  (The several-lanes kernel keeps direct accesses: on the
+// small systems it serves, the two extra barriers cost more than the scattered lines.)
 size_t step_launch_lds_bytes(const DeviceArrays& d) {
-    return std::max(step_lds_bytes(d), (size_t)d.block * (sizeof(float4) + 3 * sizeof(float)));
+    return std::max(step_lds_bytes(d), (size_t)d.block * (sizeof(float4) + 6 * sizeof(float)));
 }
 
 bool fused_actuation(const DeviceArrays& d) { return d.grp != nullptr && (d.sp_rec || d.narrow || d.packed); }
