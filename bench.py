@@ -714,7 +714,7 @@ def main(argv=None):
         "config": {"workload": w.name, "n_bodies": n_bodies, "n_masses": N, "n_springs": S, "dt": w.dt,
                    "block_masses": launch["block_masses"], "batch": launch["batch"],
                    "persistent_groups": launch["persistent_groups"], "hip_graph": mode["hip_graph"],
-                   "plain_step_us_at_creation": mode["plain_step_us"],
+                   "plain_step_us_at_creation": mode["plain_step_us"], "staged_io": mode["staged_io"],
                    "exact_difference": not args.fast_diff, "step_form": launch["step_form"],
                    "lanes_per_mass": launch["lanes_per_mass"],
                    "integrator": args.integrator},

@@ -71,6 +71,13 @@ typedef enum {
 #define CRONOS_WIDE_ENTRIES   0x200u /* keep 32-bit compact entries where 16-bit ones would fit
                                         (passive systems whose workgroup LDS slots and (k, L0)
                                         pairs fit in 16 bits; see CRONOS_FORM_NARROW)        */
+#define CRONOS_DIRECT_IO      0x1000u /* actuated systems in the 32-bit table form with one lane per
+                                        mass: read velocities and write the new state where each
+                                        lane's mass lies (the default below 256 MiB of
+                                        compulsory bytes per step, see cronos_launch_mode)    */
+#define CRONOS_STAGED_IO      0x2000u /* the same systems: velocities in and the new state out
+                                        through LDS in mass order; not with CRONOS_DIRECT_IO;
+                                        no effect on the other forms                          */
 #define CRONOS_NO_GRID        0x400u /* never take the structured-box step form (CRONOS_FORM_GRID);
                                         the other forms are chosen as without the flag        */
 #define CRONOS_FAST_DIFF      0x8u   /* skip the residual of x_j - x_i in the elongation: faster,
@@ -394,16 +401,20 @@ cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_masses, int32_
 
 /* How cronos_step enqueues its steps (not in the paper).  At creation the step is timed with
  * plain launches on the simulation's stream (9 launches that repeat one step from the current
- * buffers into the other set, HIP events; the state is unchanged): *plain_step_us receives the
+ * buffers into the other set, HIP events; the state is unchanged); *plain_step_us receives the
  * mean of the last 8 (0 where nothing was timed: CRONOS_NO_GRAPH, the default stream, the
  * resident form).  *graphs receives 1 when step calls launch HIP graphs — of 2^j steps, j < 8,
- * both buffer parities captured at creation and after cronos_set_actuation, a call's step
- * count decomposed into powers of two from the largest down — and 0 for plain launches, which
- * is the choice where *plain_step_us is 12 us or more (the device then trails the host; a
- * graph launch adds tens of microseconds before its first kernel) unless CRONOS_GRAPH is set.
- * Either way the steps' results are identical.  Either pointer may be NULL.
- * Errors: CRONOS_EINVAL for a NULL handle. */
-cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us);
+ * both buffer parities captured at creation and after cronos_set_actuation, a call's step count
+ * decomposed into powers of two from the largest down — and 0 for plain launches, which is the
+ * choice where *plain_step_us is 12 us or more (the device then trails the host; a graph launch
+ * adds tens of microseconds before its first kernel) unless CRONOS_GRAPH is set.  *staged_io
+ * receives 1 when velocities come in and the new state goes out through LDS in mass order
+ * (less HBM traffic where a workgroup's lanes take its masses out of memory order, two more
+ * barriers): for an actuated system in the 32-bit table form with one lane per mass whose
+ * compulsory bytes per step (56 per mass, 4 per incidence entry) exceed the 256 MiB Infinity
+ * Cache, or with CRONOS_STAGED_IO.  Either way the steps' results are identical.  Any pointer
+ * may be NULL.  Errors: CRONOS_EINVAL for a NULL handle. */
+cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us, int32_t* staged_io);
 
 /* Launch configuration chosen by the autotuner for a problem. */
 typedef struct {

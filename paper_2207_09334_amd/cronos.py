@@ -21,6 +21,7 @@ ALLOW_UNSTABLE, CHECK_LAYOUT, NO_GRAPH, FAST_DIFF, NO_TABLE, NO_SHIFT, SPLIT, VE
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80, 0x100, 0x200)
 NO_GRID = 0x400
 GRAPH = 0x800
+DIRECT_IO, STAGED_IO = 0x1000, 0x2000
 MASS_UNIFORM, MASS_LUMPED = 0, 1
 K_UNIFORM, K_ASSEMBLY = 0, 1
 
@@ -109,7 +110,7 @@ _SIGS = {
     "cronos_candidate_points": (C.c_int, [_p, _i64, _i32, _i32, C.c_uint64, _p]),
     "cronos_cutoff_springs": (C.c_int, [_i64, _p, _f64, _i64, _p, C.POINTER(_i64)]),
     "cronos_point_params": (C.c_int, [_i64, _p, _i64, _p, _f64, _f64, _f64, _i32, _f64, _p, _p, _p, _p]),
-    "cronos_launch_mode": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_f64)]),
+    "cronos_launch_mode": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_f64), C.POINTER(_i32)]),
     "cronos_launch_config": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
                                        C.POINTER(_i32)]),
     "cronos_autotune": (C.c_int, [C.POINTER(Desc), _i32, C.POINTER(Tune)]),
@@ -334,10 +335,11 @@ def cronos_launch_config(sim: Sim) -> dict:
 
 def cronos_launch_mode(sim: Sim) -> dict:
     """{"hip_graph": whether step calls launch HIP graphs, "plain_step_us": step time with
-    plain launches measured at creation}."""
-    g, t = _i32(), _f64(0.0)
-    _check(_lib.cronos_launch_mode(sim.handle, C.byref(g), C.byref(t)))
-    return {"hip_graph": bool(g.value), "plain_step_us": t.value}
+    plain launches measured at creation, "staged_io": whether the one-lane general forms pass
+    velocities and the new state through LDS in mass order}."""
+    g, t, io = _i32(), _f64(0.0), _i32()
+    _check(_lib.cronos_launch_mode(sim.handle, C.byref(g), C.byref(t), C.byref(io)))
+    return {"hip_graph": bool(g.value), "plain_step_us": t.value, "staged_io": bool(io.value)}
 
 
 def cronos_destroy(sim: Sim):

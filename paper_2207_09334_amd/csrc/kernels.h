@@ -30,6 +30,7 @@ struct DeviceArrays {
     int32_t batch = 4;      // incidence entries fetched per batch (2, 4 or 8)
     int32_t persistent_groups = 0;  // > 0: persistent grid of that many workgroups
     int32_t lanes = 1;              // lanes per mass (1, 2 or 4; more than 1 in the table forms only)
+    int32_t stage_io = 0;           // one-lane forms: velocities in and new state out through LDS in mass order
     float4* x[2] = {nullptr, nullptr};   // (x, y, z, 1/m); 1/m = 0 marks a fixed mass
     float* v[2] = {nullptr, nullptr};    // [n][3]
     float* mass = nullptr;               // [n]

@@ -504,7 +504,7 @@ __device__ __forceinline__ void integrate(const StepParams& p, float dtv, float4
 
 // One time step of the masses of workgroup-block b: gather, body forces, contact, friction,
 // damping, symplectic Euler, fixed masses.
-template <bool ACT, bool EXACT, int BATCH, int MODE>
+template <bool ACT, bool EXACT, int BATCH, int MODE, bool STAGE = false>
 __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepArgs& a, const StepParams& p, int b,
                                            long long n_step) {
     constexpr bool TABLE = MODE != kExplicit;
@@ -528,7 +528,7 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
     }
     // velocities read in mass order (one contiguous run), handed to each mass's lane through LDS below
     float vt0 = 0.0f, vt1 = 0.0f, vt2 = 0.0f;
-    if (base + (int)threadIdx.x < a.n) {
+    if (STAGE && base + (int)threadIdx.x < a.n) {
         const long q = 3 * (long)(base + (int)threadIdx.x);
         vt0 = a.vin[q + 0];
         vt1 = a.vin[q + 1];
@@ -570,11 +570,26 @@ __device__ __forceinline__ void step_block(float4* __restrict__ sx, const StepAr
         }
     }
     const int i = base + own;
+    if (!STAGE) {
+        if (i >= a.n) return;
+        float vx = a.vin[3 * i + 0], vy = a.vin[3 * i + 1], vz = a.vin[3 * i + 2];
+        float4 xo;
+        integrate(p, p.dtv, xi, fx, fy, fz, a.fext ? a.fext + 3 * i : nullptr, vx, vy, vz, xo,
+                  a.vstar_out ? a.vstar_out + 3 * i : nullptr);
+        a.xout[i] = xo;
+        a.vout[3 * i + 0] = vx;
+        a.vout[3 * i + 1] = vy;
+        a.vout[3 * i + 2] = vz;
+        return;
+    }
     // The lane->mass map scatters a wavefront's masses over the block, and scattered 16- and
     // 12-byte accesses reach HBM as partly used lines: velocities come in (loaded above in
     // mass order) and the new state goes out through LDS (the staged positions and tables
     // are no longer read), one contiguous run per array.  The launch provides 40 bytes of LDS
-    // per mass for it.
+    // per mass for it.  Two more barriers: a memory-bound system gains (the actuated
+    // population: 317 -> 298 us per step), a compute-bound one loses (the 16-bit-entry
+    // cantilever: 18.5 -> 20.6 us), so only the actuated 32-bit table form has the staged
+    // variant, taken where the step's bytes exceed the Infinity Cache.
     __syncthreads();
     float4* ox = sx;
     float* ov = reinterpret_cast<float*>(sx + a.block);
@@ -610,14 +625,14 @@ __device__ __forceinline__ void advance_step(const StepArgs& a, long long n_step
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.step_out = n_step + 1;
 }
 
-template <bool ACT, bool EXACT, int BATCH, int MODE>
+template <bool ACT, bool EXACT, int BATCH, int MODE, bool STAGE = false>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     constexpr bool FUSABLE = ACT && MODE != kExplicit;
     const int b = logical_block(a.nblk);
     const long long n_step = FUSABLE && a.fuse ? *a.step_in : 0;
     if (FUSABLE && a.fuse) advance_step(a, n_step);
-    if (b < a.nblk) step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b, n_step);
+    if (b < a.nblk) step_block<ACT, EXACT, BATCH, MODE, STAGE>(sx, a, p, b, n_step);
 }
 
 // Several lanes per mass (LPM = 2 or 4; compact table forms): lane j of a mass's group walks its
@@ -738,7 +753,7 @@ __global__ void __launch_bounds__(1024) step_lanes_kernel(StepArgs a, StepParams
 
 // Persistent form: a fixed grid (a multiple of 8 workgroups) walks the blocks; workgroup w runs
 // on XCD w % 8 and takes that XCD's contiguous eighth of the blocks in strides.
-template <bool ACT, bool EXACT, int BATCH, int MODE>
+template <bool ACT, bool EXACT, int BATCH, int MODE, bool STAGE = false>
 __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p) {
     extern __shared__ float4 sx[];
     const int per = (a.nblk + 7) >> 3;
@@ -750,7 +765,7 @@ __global__ void __launch_bounds__(1024) step_persistent(StepArgs a, StepParams p
     for (int j = (int)(blockIdx.x >> 3); j < per; j += stride) {
         const int b = xcd * per + j;
         if (b >= a.nblk) break;
-        step_block<ACT, EXACT, BATCH, MODE>(sx, a, p, b, n_step);
+        step_block<ACT, EXACT, BATCH, MODE, STAGE>(sx, a, p, b, n_step);
         __syncthreads();  // LDS is restaged for the next block
     }
 }
@@ -1368,11 +1383,13 @@ size_t step_lds_bytes(const DeviceArrays& d) {
     return b;
 }
 
-// Dynamic LDS of a one-lane step launch: the staging above, and room for the old velocities
-// and the new state of the block's masses (a float4 and six floats each) that step_block
-// passes through LDS in mass order.  (The several-lanes kernel keeps direct accesses: on the
-// small systems it serves, the two extra barriers cost more than the scattered lines.)
+// Dynamic LDS of a one-lane step launch: the staging above, and with stage_io room for the old
+// velocities and the new state of the block's masses (a float4 and six floats each) that
+// step_block passes through LDS in mass order.  (The several-lanes kernel keeps direct
+// accesses: on the small systems it serves, the extra barriers cost more than the scattered
+// lines.)
 size_t step_launch_lds_bytes(const DeviceArrays& d) {
+    if (!d.stage_io) return step_lds_bytes(d);
     return std::max(step_lds_bytes(d), (size_t)d.block * (sizeof(float4) + 6 * sizeof(float)));
 }
 
@@ -1433,7 +1450,13 @@ hipError_t launch_step_io(const DeviceArrays& d, const float4* xin, const float*
      : mode == kTable  ? CRONOS_GO(A, E, B, kTable)                                                  \
                        : CRONOS_GO(A, E, B, kExplicit))
     const bool act = d.grp != nullptr, ex = p.exact != 0;
-    if (d.batch == 8) {
+    if (d.stage_io && act && mode == kTable) {
+#define CRONOS_GO_S(E, B) go(step_kernel<true, E, B, kTable, true>, step_persistent<true, E, B, kTable, true>)
+        if (d.batch == 8) ex ? CRONOS_GO_S(true, 8) : CRONOS_GO_S(false, 8);
+        else if (d.batch == 2) ex ? CRONOS_GO_S(true, 2) : CRONOS_GO_S(false, 2);
+        else ex ? CRONOS_GO_S(true, 4) : CRONOS_GO_S(false, 4);
+#undef CRONOS_GO_S
+    } else if (d.batch == 8) {
         if (act) ex ? CRONOS_GO_M(true, true, 8) : CRONOS_GO_M(true, false, 8);
         else ex ? CRONOS_GO_M(false, true, 8) : CRONOS_GO_M(false, false, 8);
     } else if (d.batch == 2) {

@@ -443,19 +443,31 @@ cronos_status enqueue_plain(cronos_sim_t* s, int64_t n) {
     return CRONOS_OK;
 }
 
-// Graphs or plain launches for cronos_step.  A graph submits its launches for a fraction of
-// the host time that one launch per kernel costs, which is what a step shorter than that
-// host time needs; but each graph launch takes tens of microseconds before its first kernel
-// starts, and once the device is the slower side plain launches run no slower.  The step
-// time with plain launches is measured here, on the simulation's stream: the launches repeat
-// one step from the current buffers (positions, velocities, step counter) into the other set,
-// which the next real step overwrites anyway, so the state is unchanged.  Steps of at least
-// kPlainStepUs keep plain launches; CRONOS_GRAPH and CRONOS_NO_GRAPH override the choice.
+// Graphs or plain launches for cronos_step, and for the actuated one-lane table form whether
+// velocities and the new state pass through LDS in mass order (DeviceArrays::stage_io).
+//
+// A graph submits its launches for a fraction of the host time that one launch per kernel
+// costs, which is what a step shorter than that host time needs; but each graph launch takes
+// tens of microseconds before its first kernel starts, and once the device is the slower side
+// plain launches run no slower.  The step time with plain launches is measured here, on the
+// simulation's stream: the launches repeat one step from the current buffers (positions,
+// velocities, step counter) into the other set, which the next real step overwrites anyway,
+// so the state is unchanged.  Steps of at least kPlainStepUs keep plain launches, unless
+// CRONOS_GRAPH or CRONOS_NO_GRAPH decides.
+//
+// Staging the state through LDS turns scattered accesses into contiguous ones at the price of
+// two barriers: it pays where the step streams from HBM, i.e. where the step's compulsory
+// bytes exceed the 256 MiB of the MI355X's Infinity Cache (measured on random-walk
+// populations: 10.5 M masses 318 -> 298 us, 2.4 M masses 76.0 -> 74.1 us, 0.45 M masses 15.9
+// -> 17.0 us).  Repeating one step at a fixed parity cannot time it (the rewritten output
+// buffer stays in the cache), so the rule is by size; CRONOS_STAGED_IO / CRONOS_DIRECT_IO
+// decide otherwise.
 constexpr double kPlainStepUs = 12.0;
+constexpr double kCacheBytes = 256.0 * 1024 * 1024;
 constexpr int kModeTimedSteps = 8;
 
-cronos_status choose_launch_mode(cronos_sim_t* s, uint32_t flags) {
-    if (!s->use_graph || !s->stream || s->d.resident) return CRONOS_OK;
+// Mean time of kModeTimedSteps plain launches of one step at a fixed parity, after one untimed.
+cronos_status time_plain_steps(cronos_sim_t* s, double* us) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -473,8 +485,25 @@ cronos_status choose_launch_mode(cronos_sim_t* s, uint32_t flags) {
     (void)hipEventDestroy(e1);
     if (st == CRONOS_EDEVICE) return fail(CRONOS_EDEVICE, "create: timing the plain launches failed");
     if (st != CRONOS_OK) return st;
-    s->plain_step_us = 1e3 * (double)ms / kModeTimedSteps;
-    if (!(flags & CRONOS_GRAPH) && s->plain_step_us >= kPlainStepUs) s->use_graph = false;
+    *us = 1e3 * (double)ms / kModeTimedSteps;
+    return CRONOS_OK;
+}
+
+cronos_status choose_launch_mode(cronos_sim_t* s, uint32_t flags) {
+    if (s->d.resident) return CRONOS_OK;
+    // the staged variant exists for the actuated 32-bit table form with one lane per mass
+    const bool stage_form = s->actuated && s->d.packed && !s->d.narrow && !s->d.sp_rec && !s->d.grid &&
+                            s->d.lanes == 1;
+    if (stage_form && !(flags & CRONOS_DIRECT_IO)) {
+        // compulsory bytes per step: x (float4) and v (3 floats) read and written, 4 B per entry
+        const double bytes = (double)s->d.n * 56.0 + 4.0 * (double)s->lay.slice_ptr.back();
+        s->d.stage_io = (flags & CRONOS_STAGED_IO) || bytes > kCacheBytes ? 1 : 0;
+    }
+    if (!s->use_graph || !s->stream) return CRONOS_OK;
+    double t = 0.0;
+    TRY(time_plain_steps(s, &t));
+    s->plain_step_us = t;
+    if (!(flags & CRONOS_GRAPH) && t >= kPlainStepUs) s->use_graph = false;
     return CRONOS_OK;
 }
 
@@ -688,6 +717,10 @@ extern "C" cronos_status cronos_create(const cronos_desc* d, cronos_sim* out) {
     if ((d->flags & CRONOS_NO_GRAPH) && (d->flags & CRONOS_GRAPH)) {
         delete sim;
         return fail(CRONOS_EINVAL, "create: CRONOS_GRAPH and CRONOS_NO_GRAPH together");
+    }
+    if ((d->flags & CRONOS_STAGED_IO) && (d->flags & CRONOS_DIRECT_IO)) {
+        delete sim;
+        return fail(CRONOS_EINVAL, "create: CRONOS_STAGED_IO and CRONOS_DIRECT_IO together");
     }
 
     // ---- host arrays in the new order
@@ -1848,10 +1881,11 @@ extern "C" cronos_status cronos_launch_config(cronos_sim sim, int32_t* block_mas
     return CRONOS_OK;
 }
 
-extern "C" cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us) {
+extern "C" cronos_status cronos_launch_mode(cronos_sim sim, int32_t* graphs, double* plain_step_us, int32_t* staged_io) {
     if (!sim) return fail(CRONOS_EINVAL, "launch_mode: NULL handle");
     if (graphs) *graphs = sim->use_graph && sim->stream && !sim->d.resident ? 1 : 0;
     if (plain_step_us) *plain_step_us = sim->plain_step_us;
+    if (staged_io) *staged_io = sim->d.stage_io;
     return CRONOS_OK;
 }
 
