@@ -14,7 +14,14 @@
 // forms an entry is one 16-bit word (passive bodies: neighbour slot and index into the LDS
 // table of distinct (k, L0) pairs) or one 32-bit word (also the actuation factor).
 // Workgroups are spread so that each of the 8 XCDs gets a contiguous range of the Morton
-// order (their halos then overlap within one L2).
+// order (their halos then overlap within one L2).  A workgroup's lanes take its masses in
+// order of decreasing degree; where the step streams from HBM (actuated 32-bit form beyond the
+// Infinity Cache) a variant reads the velocities and writes the new state through LDS in mass
+// order instead of where each lane's mass lies.
+//
+// A full box of masses linked to all 26 grid neighbours takes `step_grid_kernel` instead: one
+// 512-thread workgroup per aligned 8 x 8 x 8 cube stages the cube and its one-node halo as a
+// 10 x 10 x 10 tile and reads each neighbour at a fixed tile offset, with no incidence data.
 //
 // Precision: FP32 state and FP32 accumulation.  The elongation |d| - L0 of a nearly relaxed
 // spring is a difference of nearly equal numbers; it is computed as (|d|^2 - L0^2)/(|d| + L0)
