@@ -276,7 +276,10 @@ typedef struct {
  * Euler-Bernoulli tests.  The lattice then "is copied to GPU memory" (end of "Generating a
  * Lattice"): validate the inputs, renumber (as cronos_layout_build), copy everything to device
  * memory of desc->device and bind desc->stream.  All input arrays stay the caller's.  The
- * step's HIP graphs are captured here, so no cronos_step call pays for them.  Unless CRONOS_ALLOW_UNSTABLE is set, estimates the
+ * step is timed here on that stream (nine launches that leave the state unchanged; the call
+ * waits for them and for the stream's earlier work) to choose between HIP graphs and plain
+ * launches (cronos_launch_mode), and the step's HIP graphs are captured here, so no cronos_step
+ * call pays for them.  Unless CRONOS_ALLOW_UNSTABLE is set, estimates the
  * largest natural frequency w of the rest-state system (plus the contact plane's stiffness)
  * and fails with EUNSTABLE when w * dt >= 2, where symplectic Euler diverges.
  * Errors: EINVAL, ENOMEM, EDEVICE, EUNSTABLE. */
