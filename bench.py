@@ -683,7 +683,7 @@ def main(argv=None):
         CR.cronos_step(twin, probe)
         c1.record(stream)
         c1.synchronize()
-        n_settle = max(1, int(math.ceil(args.settle_ms / (c0.elapsed_time(c1) / probe))))
+        n_settle = max(1, int(math.ceil(args.settle_ms / max(c0.elapsed_time(c1) / probe, 1e-3))))
         CR.cronos_step(twin, n_settle)
         settle = {"steps": probe + n_settle, "ms": args.settle_ms, "on": "a second copy of the workload",
                   "cold_ms_per_step": cold_ms / args.steps}

@@ -205,7 +205,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int
                                 lsum += (double)d * (double)d;
                             }
                         }
-                        const bf16 v = (bf16)(2.0f * d / (float)(g.rows * g.n_real));
+                        // rows * n_real formed in float (one rounding of the exact product, as the
+                        // integer product's conversion would give) cannot overflow 32 bits
+                        const bf16 v = (bf16)(2.0f * d / ((float)g.rows * (float)g.n_real));
                         g.dY[(long)row * g.lddy + n] = v;
                         if (n < g.n_real) g.dYt[(long)n * g.lddyt + row] = v;
                     }
