@@ -235,7 +235,7 @@ typedef struct {
     uint32_t flags;               /* CRONOS_* flags                                           */
     int32_t block_masses;         /* masses per workgroup, multiple of 64 in [64,1024]; 0 = the
                                      tuned value for this problem class if one is cached (see
-                                     cronos_autotune), else 512 for a passive system of at least
+                                     cronos_autotune), else 512 for a system of at least
                                      131,072 masses, 64 (below 32,768 masses) or 128 for a
                                      system under 131,072 masses whose lanes_per_mass is 0 too
                                      (with 4 lanes per mass; not with CRONOS_NO_TABLE,
