@@ -586,7 +586,7 @@ def main(argv=None):
     ap.add_argument("--dump", default="", help="surrogate: directory to save the data set to (npz)")
     ap.add_argument("--robots", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
-    ap.add_argument("--settle-ms", type=float, default=30.0,
+    ap.add_argument("--settle-ms", type=float, default=100.0,
                     help="milliseconds of the same steps on a second copy of the workload before the warm-up, "
                          "so that the timed steps run at the device's sustained clocks (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=2048, metavar="MIB",
