@@ -87,10 +87,6 @@ struct RolloutBuffers {
     int32_t* grp_entries = nullptr;  // [actuated entries]
     double2* gsum = nullptr;         // [n_factor]
     size_t cap_seg = 0, cap_ck = 0;
-    // the reverse sweep captured as one HIP graph, reused while everything it bakes in (the
-    // rollout's extent, the buffers, the actuation frequency) is unchanged
-    hipGraphExec_t bwd_graph = nullptr;
-    std::vector<double> bwd_key;
 };
 
 struct cronos_sim_t {
@@ -135,7 +131,6 @@ void free_device(cronos_sim_t* s) {
         for (auto& g : per)
             if (g) (void)hipGraphExecDestroy(g);
     RolloutBuffers& r = s->ro;
-    if (r.bwd_graph) (void)hipGraphExecDestroy(r.bwd_graph);
     for (hipEvent_t e : r.ev)
         if (e) (void)hipEventDestroy(e);
     if (r.side) (void)hipStreamDestroy(r.side);
@@ -1221,11 +1216,7 @@ extern "C" cronos_status cronos_set_actuation(cronos_sim sim, const double* phas
     for (size_t g = 0; g < m; ++g) amax = std::max(amax, std::fabs(amp[g]));
     sim->p.safe = (float)(4.0 * sim->rest_max * (1.0 + amax));
     drop_graphs(sim);             // graphs captured the old parameters
-    if (sim->ro.bwd_graph) {      // so did the reverse sweep's recompute (p.safe among them)
-        (void)hipGraphExecDestroy(sim->ro.bwd_graph);
-        sim->ro.bwd_graph = nullptr;
-        sim->ro.bwd_key.clear();
-    }
+
     sim->h_phase.assign(phase, phase + m);
     sim->h_amp.assign(amp, amp + m);
     return prepare_graphs(sim);
@@ -1787,39 +1778,10 @@ extern "C" cronos_status cronos_rollout_backward(cronos_sim sim, double* dphase,
     HIP_TRY(hipMemsetAsync(R.sens, 0, (size_t)entries * sizeof(double2), st));
     // the reverse sweep flips the adjoint buffers once per step
     const int cur = (int)(R.T & 1);
-    if (sim->use_graph) {
-        const std::vector<double> key = {(double)R.n0, (double)R.T, (double)R.K, (double)R.nseg,
-                                         (double)(sim->cycles >> 32), (double)(sim->cycles & 0xFFFFFFFFull), sim->omega,
-                                         (double)(uintptr_t)R.ck_x, (double)(uintptr_t)R.seg_x[0], (double)(uintptr_t)R.seg_x[1],
-                                         (double)(uintptr_t)R.seg_f[0], (double)(uintptr_t)R.seg_f[1],
-                                         (double)(uintptr_t)R.xb[0], (double)(uintptr_t)R.sens};
-        if (!R.bwd_graph || R.bwd_key != key) {
-            if (R.bwd_graph) {
-                HIP_TRY(hipStreamSynchronize(st));
-                (void)hipGraphExecDestroy(R.bwd_graph);
-                R.bwd_graph = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const cronos_status cs = enqueue_reverse_sweep(sim);
-            const hipError_t e = hipStreamEndCapture(st, &g);
-            if (cs != CRONOS_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return cs;
-            }
-            if (e != hipSuccess) return fail(CRONOS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-            const hipError_t ei = hipGraphInstantiate(&R.bwd_graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) {
-                R.bwd_graph = nullptr;
-                return fail(CRONOS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
-            }
-            R.bwd_key = key;
-        }
-        HIP_TRY(hipGraphLaunch(R.bwd_graph, st));
-    } else {
-        TRY(enqueue_reverse_sweep(sim));
-    }
+    // plain launches on the two streams: captured as one HIP graph the same sweep ran its
+    // recompute and adjoint branches one after the other (quadruped, 2000 steps: 26.3-27.3 ms
+    // against 20.7 ms)
+    TRY(enqueue_reverse_sweep(sim));
     // per-group sums of the actuation sensitivities (FP64), then the chain rule to phase and amplitude
     const int32_t G = sim->d.n_factor;
     if ((dphase || damp) && G > 0 && sim->actuated) {

@@ -198,14 +198,14 @@ def test_autograd_function_drives_torch():
     assert np.array_equal(phase.grad.numpy(), dp) and np.array_equal(amp.grad.numpy(), da)
 
 
-def test_graph_captured_sweep_follows_amplitude_increases_in_the_shifted_frame():
+def test_repeated_sweeps_follow_amplitude_increases_in_the_shifted_frame():
     """Without the contact plane the device frame is shifted, so wavefronts take the plain
     coordinate difference when all their masses lie beyond the safe distance, which grows with
-    the largest amplitude.  Raising the amplitudes between calls (0.02 -> 0.1 -> 0.25) must drop
-    the captured sweep along with the parameters it captured: every call's gradients equal the
-    plain launches' bit for bit."""
+    the largest amplitude.  Raising the amplitudes between calls (0.02 -> 0.1 -> 0.25) must
+    reach every launch that depends on it (the forward's step graphs are captured again): every
+    call's gradients equal those of a simulation on plain launches bit for bit."""
     w = _actuated_cube(ground=False)
-    say("case: adjoint sweep graph vs plain launches in the shifted frame, amplitudes raised per call")
+    say("case: adjoint sweeps, default launches vs plain launches in the shifted frame, amplitudes raised per call")
     sim_g, lat, x0 = PR.create(w)
     sim_p, _, _ = PR.create(w, flags=CR.NO_GRAPH)
     # not the centre of mass: with no contact plane its motion ignores the internal forces, so
@@ -228,12 +228,12 @@ def test_graph_captured_sweep_follows_amplitude_increases_in_the_shifted_frame()
     sim_p.close()
 
 
-def test_graph_captured_sweep_matches_plain_launches():
-    """The reverse sweep is captured once as a HIP graph and replayed while the rollout's extent
-    and frequency stay the same: over repeated calls with new phases and amplitudes between
-    them (and other work on the stream in between), bitwise the gradients of plain launches."""
+def test_repeated_sweeps_match_plain_launches():
+    """Repeated rollouts and reverse sweeps on one simulation, with new phases and amplitudes
+    between them (and other work on the stream in between), give bitwise the gradients of a
+    simulation on plain launches."""
     w = _actuated_cube(ground=True)
-    say("case: adjoint reverse sweep, HIP graph replays vs plain launches, 3 calls")
+    say("case: adjoint reverse sweeps, default launches vs plain launches, 3 calls")
     sim_g, lat, x0 = PR.create(w)
     sim_p, _, _ = PR.create(w, flags=CR.NO_GRAPH)
     lw = np.zeros_like(lat.x)
