@@ -192,6 +192,92 @@ __global__ void __launch_bounds__(1024) modes_apply_lds_kernel(ApplyArgs a, cons
     if (t == 0) part[b] = sum;
 }
 
+// y = A q for a full box in the structured-box layout (one 512-mass workgroup per aligned
+// 8 x 8 x 8 Morton cube, every mass linked to its 26 grid neighbours, as the step's
+// structured-box form): the cube and its one-node halo are staged as a 10 x 10 x 10 tile of
+// positions and u = M^-1/2 q, each neighbour sits at a fixed tile offset, k comes from the
+// table per (boundary class, direction) and L0 per direction kind, so no incidence data is
+// read.  Halo cells outside the box hold a far position and u = 0 with k = 0: no contribution.
+struct GridApplyArgs {
+    const float4* __restrict__ x;
+    const double* __restrict__ ism;
+    const int32_t* __restrict__ halo;   // [nblk][488] new index of each halo cell, -1 outside
+    const int4* __restrict__ org;       // [nblk] grid coordinates of the block's first node
+    const float* __restrict__ kcls;     // [27][26] k per (boundary class, direction)
+    const uint32_t* __restrict__ tab;   // [512] lane's tile cell | lx << 10 | ly << 13 | lz << 16,
+                                        // then [488] tile cell of each halo slot
+    int nx, ny, nz;
+    float l0[3];                        // rest length per direction kind (1, 2, 3 non-zero offsets)
+    int ground;
+    float ground_z, ground_k;
+};
+
+constexpr int kTilePitch = 10, kTileCells = 1000, kTileHalo = 488, kTileMasses = 512;
+
+__global__ void __launch_bounds__(kTileMasses) modes_apply_grid_kernel(GridApplyArgs a, const double* __restrict__ q,
+                                                                       double* __restrict__ y,
+                                                                       double* __restrict__ part) {
+    __shared__ float4 tx[kTileCells];
+    __shared__ double tu[3 * kTileCells];
+    __shared__ float kc[27 * 26];
+    __shared__ double red[kMaxWaves + 1];
+    const int b = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int i = b * kTileMasses + t;   // the box holds whole cubes: i < n
+    const uint32_t info = a.tab[t];
+    const int cell = (int)(info & 1023u);
+    {
+        const double sm = a.ism[i];
+        tx[cell] = a.x[i];
+        tu[3 * cell + 0] = sm * q[3 * i + 0];
+        tu[3 * cell + 1] = sm * q[3 * i + 1];
+        tu[3 * cell + 2] = sm * q[3 * i + 2];
+    }
+    for (int h = t; h < kTileHalo; h += kTileMasses) {
+        const int g = a.halo[(long)b * kTileHalo + h];
+        const int c = (int)a.tab[kTileMasses + h];
+        float4 xm = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+        if (g >= 0) {
+            const double sm = a.ism[g];
+            xm = a.x[g];
+            u0 = sm * q[3 * g + 0];
+            u1 = sm * q[3 * g + 1];
+            u2 = sm * q[3 * g + 2];
+        }
+        tx[c] = xm;
+        tu[3 * c + 0] = u0;
+        tu[3 * c + 1] = u1;
+        tu[3 * c + 2] = u2;
+    }
+    for (int r = t; r < 27 * 26; r += kTileMasses) kc[r] = a.kcls[r];
+    const int4 o = a.org[b];
+    const int gx = o.x + (int)((info >> 10) & 7u), gy = o.y + (int)((info >> 13) & 7u), gz = o.z + (int)((info >> 16) & 7u);
+    const int cls = (gx == 0 ? 0 : gx == a.nx - 1 ? 2 : 1) + 3 * (gy == 0 ? 0 : gy == a.ny - 1 ? 2 : 1) +
+                    9 * (gz == 0 ? 0 : gz == a.nz - 1 ? 2 : 1);
+    __syncthreads();
+    const float4 xi = tx[cell];
+    const double u0 = tu[3 * cell + 0], u1 = tu[3 * cell + 1], u2 = tu[3 * cell + 2];
+    double k0 = 0.0, k1 = 0.0, k2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 26; ++d) {
+        const int e = d < 13 ? d : d + 1;   // the 3 x 3 x 3 stencil without its centre, (dz, dy, dx) order
+        const int ox = e % 3 - 1, oy = (e / 3) % 3 - 1, oz = e / 9 - 1;
+        const int kind = (ox != 0) + (oy != 0) + (oz != 0) - 1;
+        const int nc = cell + (oz * kTilePitch + oy) * kTilePitch + ox;
+        spring_hessian(xi, tx[nc], u0, u1, u2, tu[3 * nc], tu[3 * nc + 1], tu[3 * nc + 2], (double)kc[26 * cls + d],
+                       (double)a.l0[kind], k0, k1, k2);
+    }
+    if (a.ground && xi.z < a.ground_z) k2 += (double)a.ground_k * u2;
+    const double si = a.ism[i];
+    const double y0 = si * k0, y1 = si * k1, y2 = si * k2;
+    y[3 * i] = y0;
+    y[3 * i + 1] = y1;
+    y[3 * i + 2] = y2;
+    const double dot = q[3 * i] * y0 + q[3 * i + 1] * y1 + q[3 * i + 2] * y2;
+    const double sum = workgroup_sum(dot, red);
+    if (t == 0) part[b] = sum;
+}
+
 // y = A q for the masses of workgroup-block b, and the block's part of q . y; neighbours read
 // from global memory (used when the staged form's LDS would not fit).
 __global__ void __launch_bounds__(1024) modes_apply_kernel(ApplyArgs a, const double* __restrict__ q,
@@ -287,7 +373,13 @@ hipError_t launch_modes_iteration(const DeviceArrays& d, int cur, const StepPara
     ApplyArgs a{d.x[cur], m.ism, d.slice_ptr, d.nbr, d.kl, d.grp, d.factor, d.halo_ptr, d.halo_idx, d.lane_mass,
                 n, d.block, d.lds_slots, p.ground, p.ground_z, p.ground_k};
     const size_t lds = (size_t)d.lds_slots * (sizeof(float4) + 3 * sizeof(double));
-    if (lds <= kModesMaxLds)
+    if (d.grid) {
+        GridApplyArgs ga{d.x[cur], m.ism, d.grid_halo, d.grid_org, d.grid_k, d.grid_tab,
+                         d.grid_dim[0], d.grid_dim[1], d.grid_dim[2], {d.grid_l0[0], d.grid_l0[1], d.grid_l0[2]},
+                         p.ground, p.ground_z, p.ground_k};
+        hipLaunchKernelGGL(modes_apply_grid_kernel, dim3((unsigned)d.nblk), dim3(kTileMasses), 0, st, ga, q, m.y,
+                           m.part_a);
+    } else if (lds <= kModesMaxLds)
         hipLaunchKernelGGL(modes_apply_lds_kernel, dim3((unsigned)d.nblk), dim3(d.block), lds, st, a, q, m.y, m.part_a);
     else
         hipLaunchKernelGGL(modes_apply_kernel, dim3((unsigned)d.nblk), dim3(d.block), 0, st, a, q, m.y, m.part_a);

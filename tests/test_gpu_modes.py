@@ -112,3 +112,24 @@ def test_contact_plane_stiffness_enters():
     say(f"  on the plane: device {dev} ({iters} steps); oracle {om}; without the plane {free}")
     assert dev == pytest.approx(om, rel=1e-7)
     assert om[0] > 1.01 * free[0]
+
+
+def test_structured_box_apply_matches_the_general_one():
+    """A full box in the structured-box layout (512-mass cubes, neighbours at fixed tile
+    offsets, no incidence data) gives the frequencies of the general incidence-list operator on
+    the same system to FP64 rounding (the springs are summed in another order), at rest and
+    deformed (the geometric term), with and without the contact plane."""
+    for w, over in ((W.cantilever(64, 16, 16), dict(gravity=(0.0, 0.0, 0.0))),
+                    (W.cube_drop(24), dict(ground_z=0.12))):
+        lat = L.build(w)
+        rng = np.random.default_rng(3)
+        x0 = lat.x + rng.normal(0.0, 2e-4, lat.x.shape) * (~np.asarray(lat.pinned, bool))[:, None]
+        sims = [PR.create(w, x0=x0, block_masses=512, flags=f, **over)[0] for f in (0, CR.NO_GRID)]
+        forms = [CR.cronos_launch_config(s)["step_form"] for s in sims]
+        assert forms == ["grid", "narrow"]
+        (og, ig), (on, inn) = [CR.cronos_natural_frequencies(s, n_modes=2, tol=1e-10) for s in sims]
+        say(f"  {w.name}: grid {og} ({ig} steps), general {on} ({inn} steps)")
+        assert len(og) == len(on) == 2
+        np.testing.assert_allclose(og, on, rtol=1e-8)
+        for s in sims:
+            s.close()
