@@ -435,7 +435,7 @@ def surrogate_bench(args) -> dict:
     """Surrogate screening vs the plain batched simulator.  Morphology pools of `pool` robots
     (seed 4, disjoint robot-index ranges) are each simulated under `draws` actuation draws
     (5000 steps each); the robots of the first `pools` pools train the network, those of the
-    next `held_pools` pools are held-out candidates judged by the simulator."""
+    next `held_pools` pools are held-out candidates scored by the simulator."""
     import numpy as np
 
     from paper_2207_09334_amd import cronos as CR

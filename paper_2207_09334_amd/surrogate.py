@@ -1,4 +1,4 @@
-"""Surrogate screening with the simulator as judge and fallback.
+"""Surrogate screening with the simulator as arbiter and fallback.
 
 * ``Pool``: a population of robots stepped together as one batched simulation; one rollout
   draw sets every robot's actuation (phases, amplitudes), restarts from the rest state, runs

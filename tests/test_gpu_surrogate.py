@@ -130,7 +130,7 @@ def test_learning_rate_schedule():
 
 
 def test_screening_pipeline_small():
-    """A 48-robot pool, 8 actuation draws of 400 steps: the judge (simulator) is bitwise
+    """A 48-robot pool, 8 actuation draws of 400 steps: the arbiter (simulator) is bitwise
     repeatable, training runs on the device, predictions are finite, out-of-distribution
     candidates are flagged and always handed to the simulator."""
     from paper_2207_09334_amd import surrogate as SG
@@ -156,7 +156,7 @@ def test_screening_pipeline_small():
 
 def test_trained_network_gains_over_the_method_without_it():
     """What the trained network adds: on robots it never saw in training (a pool of 256 random
-    -walk robots, 8 actuation draws each, rollouts of the configured 5000 steps judged by the
+    -walk robots, 8 actuation draws each, rollouts of the configured 5000 steps scored by the
     simulator), the network's error on the displacement vector is far below that of the best
     prediction without it (the training mean).  The forward (x) component alone and the
     top-10% recall of a screen on it are reported, not asserted: at this data size the
